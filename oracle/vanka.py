@@ -1,0 +1,99 @@
+"""Space-time cell Vanka smoother (test infrastructure).
+
+Eq. (vanka0), (vanka): for every space-time cell T = K x I_n the local matrix
+A_T = R_T S R_T^T over all dofs of T (all k+1 temporal dofs of I_n; reading
+G7: the assembled level matrix restricted to T, neighbour contributions
+included), the additive sum of local solves weighted by the inverse valence
+(the remark on patch construction in Sec. 4.2; reading G9), and
+x <- x + omega * D^{-1} sum_T R_T^T A_T^{-1} R_T (b - S x).
+
+Since Dirichlet rows and columns of S are the identity, taking ALL dofs of the
+cell (Dirichlet ones included) pads A_T with identity rows/columns; the update
+is masked to zero on Dirichlet dofs.  A_T is the same for every subinterval
+(uniform tau), so one inverse per spatial cell is stored.
+"""
+import numpy as np
+
+from .spacetime import SpaceTimeLevel
+
+
+def cell_dofs(L: SpaceTimeLevel, n):
+    """Global indices of all dofs of every space-time cell K x I_n:
+    array (n_cells, b) in the local order [a][comp][node] then [a][mode]."""
+    s = L.sp
+    cn = s.vdofs.cell_nodes                                  # (nc, Q^d)
+    nc = s.mesh.n_cells
+    parts = []
+    for a in range(L.nt):
+        base = L.v_index(n, a).start
+        for c in range(s.d):
+            parts.append(base + c * s.n_nodes + cn)
+    for a in range(L.nt):
+        base = L.p_index(n, a).start
+        parts.append(base + np.arange(nc)[:, None] * s.C + np.arange(s.C)[None, :])
+    return np.concatenate(parts, axis=1)
+
+
+def local_matrices_literal(L: SpaceTimeLevel):
+    """A_T = S[idx_T, idx_T] extracted from the literal global CSR."""
+    S = L.csr()
+    idx = cell_dofs(L, 0)
+    return np.array([S[i][:, i].toarray() for i in idx])
+
+
+def local_matrices_factored(L: SpaceTimeLevel):
+    """The same blocks built from the spatial matrices (Kronecker form of the
+    per-subinterval block D); used where the literal CSR is too large."""
+    s = L.sp
+    cn = s.vdofs.cell_nodes
+    nc, d, C, nt = s.mesh.n_cells, s.d, s.C, L.nt
+    out = []
+    for T in range(nc):
+        iv = np.concatenate([c * s.n_nodes + cn[T] for c in range(d)])
+        ip = T * C + np.arange(C)
+        fv = ~s.vel_boundary[iv]
+        keep = np.outer(fv, fv).astype(float)
+        Mloc = s.Mh[iv][:, iv].toarray() * keep
+        Aloc = s.Ah[iv][:, iv].toarray() * keep
+        Bloc = s.B[ip][:, iv].toarray() * fv[None, :].astype(float)
+        Avv = np.kron(L.K, Mloc) + np.kron(L.Mtau, Aloc)
+        Avv += np.kron(np.eye(nt), np.diag((~fv).astype(float)))
+        Avp = -np.kron(L.Mtau, Bloc.T)
+        Apv = -np.kron(L.Mtau, Bloc)
+        App = np.zeros((nt * C, nt * C))
+        out.append(np.block([[Avv, Avp], [Apv, App]]))
+    return np.array(out)
+
+
+class Vanka:
+    def __init__(self, L: SpaceTimeLevel, omega, literal=None):
+        self.L = L
+        self.omega = float(omega)
+        if literal is None:
+            literal = L.ndofs <= 200_000
+        A = local_matrices_literal(L) if literal else local_matrices_factored(L)
+        self.inv = np.linalg.inv(A)
+        self.idx = [cell_dofs(L, n) for n in range(L.N)]
+        # valence D: number of spatial cells sharing the dof (pressure: 1)
+        val = np.zeros(L.ndofs)
+        for n in range(L.N):
+            np.add.at(val, self.idx[n].ravel(), 1.0)
+        self.inv_val = 1.0 / val
+        self.dmask = L.dirichlet_mask()
+
+    def correction(self, r):
+        """sum_T R_T^T A_T^{-1} R_T r, weighted by 1/valence, zero on Dirichlet."""
+        u = np.zeros_like(r)
+        for n in range(self.L.N):
+            idx = self.idx[n]
+            y = np.einsum("cij,cj->ci", self.inv, r[idx])
+            u += np.bincount(idx.ravel(), weights=y.ravel(), minlength=len(r))
+        u *= self.inv_val
+        u[self.dmask] = 0.0
+        return u
+
+    def smooth(self, b, x, steps, apply):
+        """Eq. (vanka): x <- x + omega * smoother(S, b - S x), `steps` times."""
+        for _ in range(steps):
+            x = x + self.omega * self.correction(b - apply(x))
+        return x
