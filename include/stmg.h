@@ -1,0 +1,185 @@
+/*
+ * stmg.h - C ABI of the MI355X hp space-time multigrid library.
+ *
+ * The library solves the slab system of the instationary Stokes equations
+ * discretised with Q_{r+1}/P_r^disc elements in space and DG(k) in time
+ * (Margenberg, Bause, Munch, arXiv 2502.09159: Problem "Discrete variational
+ * problem", Sec. 2.2; algebraic form Eq. (InAlg), (DefDtauh), (GloSys) of
+ * Sec. 3.2) with FGMRES preconditioned by one hp space-time multigrid V-cycle
+ * (Alg. 1 of Sec. 4.3; transfers of App. A; cell Vanka smoother Eq. (vanka0),
+ * (vanka) of Sec. 4.2).
+ *
+ * Conventions
+ *  - Every function returns stmg_status (0 = ok, < 0 = error); no C++
+ *    exception crosses the ABI.  stmg_last_error() returns a message for the
+ *    last failing call on a context (owned by the context).
+ *  - Vectors passed to compute calls are caller-owned DEVICE pointers to
+ *    contiguous FP64 arrays in the layout of Eq. (DefX):
+ *        X = (V_1, P_1, ..., V_N, P_N),  V_n = (V_n^1..V_n^{k+1}),
+ *        P_n = (P_n^1..P_n^{k+1});
+ *    V_n^a is component-major over the global Gauss-Lobatto velocity nodes
+ *    (nn = n (r+1) + 1 per direction, x fastest), P_n^a is cell-major (cells
+ *    x fastest) over the C(r+d, d) shifted-Legendre modes of each cell,
+ *    ordered by total degree, then with the x exponent largest first.
+ *    Dirichlet velocity dofs are part of the vector; the operator acts as
+ *    the identity on them.
+ *  - The caller must not free or resize vectors during a call.  All calls
+ *    are synchronous: work is issued on the context's stream and completed
+ *    before the call returns.  A context is used by one host thread at a
+ *    time.
+ *  - Level 0 is the finest level (the paper numbers levels coarsest first).
+ *  - The context owns all setup data (geometry, smoother factors, coarse
+ *    inverse, work vectors) and frees it in stmg_destroy.
+ */
+#ifndef STMG_H
+#define STMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STMG_OK = 0,
+  STMG_EINVAL = -1,       /* bad argument: null pointer, unsupported r/k/d/N */
+  STMG_ENOMEM = -2,       /* host or device allocation failed */
+  STMG_EDEVICE = -3,      /* a HIP runtime call failed */
+  STMG_ENOCONV = -4,      /* solve reached max_it before the tolerance */
+  STMG_ESINGULAR = -5,    /* a local or coarse factorisation broke down */
+  STMG_EUNSUPPORTED = -6  /* feature not available in this build */
+} stmg_status;
+
+typedef struct stmg_ctx stmg_ctx;
+
+typedef enum {
+  STMG_FP64 = 0,        /* every level in FP64 */
+  STMG_MIXED_FP32 = 1   /* V-cycle in FP32 inside FP64 FGMRES */
+} stmg_precision;
+
+typedef enum {
+  STMG_VANKA_FACTORED = 0, /* local inverse applied in Schur-factored form */
+  STMG_VANKA_DENSE = 1     /* local inverse stored as one dense b x b block */
+} stmg_vanka_mode;
+
+/* nu(x) callback: evaluate the viscosity at npts physical points xyz
+ * (npts x dim, row-major) into nu_out (npts).  Called on the host during
+ * stmg_setup only. */
+typedef void (*stmg_nu_fn)(int npts, const double* xyz, double* nu_out, void* user);
+
+typedef struct {
+  int dim;               /* 2 or 3 */
+  int n_cells_1d;        /* fine mesh: n^d cells on [0,1]^d, n a power of two */
+  int n_coarse_1d;       /* cells per direction of the coarsest h-level */
+  double deform_amp;     /* vertices x_i += amp * prod_j sin(2 pi x_j) */
+  int r, k;              /* velocity Q_{r+1}, pressure P_r^disc, DG(k) */
+  int n_sub;             /* N subintervals of the slab */
+  double tau;            /* uniform subinterval length */
+  double nu;             /* constant viscosity (used when nu_fn == NULL) */
+  stmg_nu_fn nu_fn;      /* optional nu(x) */
+  void* nu_user;
+  int r_min, k_min;      /* p-coarsening floors (>= 1 and >= 0) */
+  int time_h_coarsening; /* 1: halve N on the coarsest spatial h-steps */
+  int nu_pre, nu_post;   /* Vanka sweeps before/after the coarse correction */
+  double omega;          /* Vanka relaxation */
+  int precision;         /* stmg_precision */
+  int vanka_mode;        /* stmg_vanka_mode */
+  int device;            /* HIP device ordinal */
+  void* stream;          /* hipStream_t to issue work on, or NULL (default) */
+} stmg_params;
+
+/* Fill p with the defaults (3D, n=4, r=1, k=1, N=2, tau=0.05, nu=1,
+ * r_min=k_min=1, time h-coarsening on, one pre/post sweep, omega=0.8, FP64,
+ * factored Vanka, device 0, default stream). */
+stmg_status stmg_default_params(stmg_params* p);
+
+/* Build the level list of the hp hierarchy without touching a GPU
+ * (Sec. 4.4: p before h, space before time, space-time coarsening at the
+ * coarse end).  levels_out receives up to max_levels rows of
+ * (n_cells_1d, r, k, n_sub); *n_levels the number of levels (finest first). */
+stmg_status stmg_hierarchy(const stmg_params* p, int max_levels, int* levels_out, int* n_levels);
+
+/* Set up all levels on the device: mesh hierarchy, geometry, temporal
+ * matrices (Eq. (DefKMC)), cell-patch matrices and their FP64
+ * factorisations (Eq. (vanka0)), transfer tables (App. A) and the bordered
+ * coarse-level inverse.  *out receives a new context. */
+stmg_status stmg_setup(const stmg_params* p, stmg_ctx** out);
+stmg_status stmg_destroy(stmg_ctx* ctx);
+const char* stmg_last_error(const stmg_ctx* ctx);
+
+/* Record per-phase device times (smoother, rest of the V-cycle, outer
+ * operator applies, other) in stmg_solve_info; adds event overhead. */
+stmg_status stmg_set_phase_timing(stmg_ctx* ctx, int on);
+
+/* Sizes of a level: total dofs, velocity dofs per slice, pressure dofs per
+ * slice; *n_levels receives the number of levels. */
+stmg_status stmg_sizes(const stmg_ctx* ctx, int level, int64_t* n_dofs, int64_t* n_vel_space,
+                       int64_t* n_p_space, int* n_levels);
+
+/* y = S_level x (Eq. (GloSys) on that level), FP64.  x and y must not alias. */
+stmg_status stmg_apply_operator(stmg_ctx* ctx, int level, const double* x, double* y);
+
+/* r = b - S_level x, FP64. */
+stmg_status stmg_residual(stmg_ctx* ctx, int level, const double* b, const double* x, double* r);
+
+/* `steps` cell Vanka iterations x <- x + omega D^{-1} sum_T R_T^T A_T^{-1} R_T (b - S x)
+ * (Eq. (vanka) with valence weighting), FP64, x updated in place. */
+stmg_status stmg_smooth(stmg_ctx* ctx, int level, const double* b, double* x, int steps);
+
+/* x += omega D^{-1} sum_T R_T^T A_T^{-1} R_T r: the smoother's correction
+ * step alone (the local solves of Eq. (vanka0) for a given residual r), in
+ * the context's precision (inputs cast when the context is mixed). */
+stmg_status stmg_vanka_correction(stmg_ctx* ctx, int level, const double* r, double* x);
+
+/* Benchmark helper: run one kernel class `reps` times back to back on the
+ * level's internal work vectors, in the context's precision, on the
+ * context's stream, and return the mean device time of one application in
+ * *avg_ms (HIP events).  which = 0: Vanka correction (all colours);
+ * which = 1: operator residual b - S x (all colours).  The work vectors'
+ * contents are overwritten. */
+stmg_status stmg_kernel_time(stmg_ctx* ctx, int which, int level, int reps, double* avg_ms);
+
+/* coarse = P^T fine (restriction, App. A) from `level` to `level + 1`. */
+stmg_status stmg_restrict(stmg_ctx* ctx, int level, const double* fine, double* coarse);
+
+/* fine = P coarse (prolongation, App. A) from `level + 1` to `level`. */
+stmg_status stmg_prolongate(stmg_ctx* ctx, int level, const double* coarse, double* fine);
+
+/* x = exact solution on the coarsest level with per-slice mean-zero pressure
+ * (bordered FP64 inverse; Alg. 1 step 3). */
+stmg_status stmg_coarse_solve(stmg_ctx* ctx, const double* b, double* x);
+
+/* x = V(b): one V-cycle from a zero initial guess on the finest level, in the
+ * context's precision (Alg. 1 with Alg. 4-7). */
+stmg_status stmg_vcycle(stmg_ctx* ctx, const double* b, double* x);
+
+typedef struct {
+  int iterations;          /* preconditioner applications */
+  double rel_residual;     /* explicit ||b - S x|| / ||b|| at exit */
+  double t_solve_s;        /* wall time of the solve (device events) */
+  double t_smoother_s;     /* time in Vanka sweeps */
+  double t_mg_other_s;     /* V-cycle minus smoothing (applies, transfers, coarse) */
+  double t_operator_s;     /* FGMRES operator applies outside the V-cycle */
+  double t_other_s;        /* orthogonalisation and the rest */
+  int learned_disabled;    /* 1 if the learned correction was switched off */
+  int history_len;
+  const double* history;   /* residual estimates, owned by the context */
+} stmg_solve_info;
+
+/* FGMRES (right preconditioned by stmg_vcycle, CGS2, x0 = 0) on the finest
+ * level until ||b - S x|| <= rtol ||b|| (explicitly rechecked).  Returns
+ * STMG_ENOCONV if max_it preconditioner applications were not enough (x then
+ * holds the last iterate).  info may be NULL.  The returned x has mean-zero
+ * pressure in every slice. */
+stmg_status stmg_solve(stmg_ctx* ctx, const double* b, double* x, double rtol, int max_it,
+                       stmg_solve_info* info);
+
+/* x <- x with the L2 mean of the pressure removed in every slice (device
+ * vector, finest level). */
+stmg_status stmg_project_pressure_mean_zero(stmg_ctx* ctx, double* x);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STMG_H */

@@ -41,14 +41,15 @@ def local_matrices_literal(L: SpaceTimeLevel):
     return np.array([S[i][:, i].toarray() for i in idx])
 
 
-def local_matrices_factored(L: SpaceTimeLevel):
+def local_matrices_factored(L: SpaceTimeLevel, cells=None):
     """The same blocks built from the spatial matrices (Kronecker form of the
-    per-subinterval block D); used where the literal CSR is too large."""
+    per-subinterval block D); used where the literal CSR is too large.
+    `cells` restricts the construction to a subset of cells."""
     s = L.sp
     cn = s.vdofs.cell_nodes
     nc, d, C, nt = s.mesh.n_cells, s.d, s.C, L.nt
     out = []
-    for T in range(nc):
+    for T in (range(nc) if cells is None else cells):
         iv = np.concatenate([c * s.n_nodes + cn[T] for c in range(d)])
         ip = T * C + np.arange(C)
         fv = ~s.vel_boundary[iv]

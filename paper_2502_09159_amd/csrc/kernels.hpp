@@ -1,0 +1,75 @@
+// Device kernels of the hp space-time multigrid (gfx950).  Host-callable
+// launchers; all work is enqueued on the given stream.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace stmg {
+
+// Per-level sizes shared by the kernels.
+struct LevelArgs {
+  int d, n, q, Q, nn, nt, C, N, nloc;
+  int64_t nodes, Mv, Mp, slab;
+};
+
+// Small per-level tables, in the arithmetic type T, packed as
+// [S (QxQ) | Dg (QxQ) | gx (Q) | gw (Q) | K (nt x nt) | phim1 (nt) | coef (nt) | psi (nloc x C)].
+inline int table_size(int Q, int nt, int nloc, int C) { return 2 * Q * Q + 2 * Q + nt * nt + 2 * nt + nloc * C; }
+
+// Operator: y = S x (mode 0) or y = b - S x (mode 1), colored, deterministic.
+template <typename T>
+hipError_t launch_apply(const LevelArgs& L, const double* verts, const T* nu_q, T nu_const, const T* tab,
+                        const T* x, const T* b, T* y, int mode, hipStream_t s);
+
+// Vanka correction with factored local inverses: x += omega D^-1 sum R^T A^-1 R r.
+template <typename T>
+hipError_t launch_vanka_factored(const LevelArgs& L, const T* As_inv, const T* Bm, const T* F, const T* Hinv,
+                                 const T* coef, const T* r, T* x, T omega, hipStream_t s);
+// Same with one dense local inverse per cell.
+template <typename T>
+hipError_t launch_vanka_dense(const LevelArgs& L, const T* Ainv, const T* r, T* x, T omega, hipStream_t s);
+
+// Transfers.  Tables (device): P1 (nnf x nnc), P1T (nnc x nnf) row-major with
+// nonzero ranges; E (npos x Cf x Cc); Pt (ntf x ntc) row-major.
+struct TransferDev {
+  int nnf, nnc, npos, ntf, ntc;
+  bool time_change;
+};
+template <typename T>
+hipError_t launch_prolongate_add(const LevelArgs& F, const LevelArgs& Cs, const TransferDev& t,
+                                 const T* P1, const int* rlo, const int* rhi, const T* E, const T* Pt,
+                                 const T* xc, T* xf, T* tmp1, T* tmp2, T* tmp3, hipStream_t s);
+template <typename T>
+hipError_t launch_restrict(const LevelArgs& F, const LevelArgs& Cs, const TransferDev& t, const T* P1T,
+                           const int* clo, const int* chi, const T* E, const T* Pt, const T* rf, T* bc, T* tmp1,
+                           T* tmp2, T* tmp3, hipStream_t s);
+
+// Coarse solve x = Cinv b (Cinv FP64, nd x nd row-major).
+template <typename T>
+hipError_t launch_coarse(int64_t nd, const double* Cinv, const T* b, T* x, hipStream_t s);
+
+// Vector helpers.
+template <typename T>
+hipError_t launch_fill(T* x, T v, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_axpy(T* y, T a, const T* x, int64_t n, hipStream_t s);  // y += a x
+hipError_t launch_cast_d2f(const double* a, float* b, int64_t n, hipStream_t s);
+hipError_t launch_cast_f2d(const float* a, double* b, int64_t n, hipStream_t s);
+// Multi-dot: out[i] = V_i . w for i < nv (V rows of length n, stride ldv);
+// partial buffer needs nv * 1024 doubles.
+hipError_t launch_multidot(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* partial,
+                           double* out, hipStream_t s);
+// w -= sum_i h_i V_i (h on device)
+hipError_t launch_multi_axpy(double* w, const double* V, int64_t ldv, int nv, const double* h, int64_t n,
+                             hipStream_t s);
+// x += sum_i y_i Z_i
+hipError_t launch_combine(double* x, const double* Z, int64_t ldz, int nv, const double* y, int64_t n,
+                          hipStream_t s);
+// scale: y = x / a
+hipError_t launch_scale_copy(double* y, const double* x, double inv, int64_t n, hipStream_t s);
+// pressure mean removal per slice; mom: ncells x C moments; partial >= N nt 1024
+hipError_t launch_project_pressure(const LevelArgs& L, const double* mom, double volume, double* x,
+                                   double* partial, hipStream_t s);
+
+}  // namespace stmg

@@ -1,0 +1,761 @@
+// C ABI of the hp space-time multigrid library (include/stmg.h): context
+// set-up, device uploads, the V-cycle (Alg. 1 with Alg. 4-7) and FGMRES.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#include "../../include/stmg.h"
+#include "host.hpp"
+#include "kernels.hpp"
+
+using namespace stmg;
+
+namespace {
+
+struct DeviceError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define HIPCHK(expr)                                                                              \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      throw DeviceError(std::string(#expr) + " failed: " + hipGetErrorString(e_));                \
+  } while (0)
+
+// tracked device allocations, freed with the context
+struct Pool {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  template <typename T>
+  T* alloc(size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) throw Error(STMG_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    ptrs.push_back(p);
+    bytes += n * sizeof(T);
+    return static_cast<T*>(p);
+  }
+  template <typename T, typename S>
+  T* upload(const std::vector<S>& v, hipStream_t s) {
+    T* d = alloc<T>(v.size());
+    if (v.empty()) return d;
+    if constexpr (std::is_same<T, S>::value) {
+      HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));  // the host vector may be a temporary
+    } else {
+      std::vector<T> c(v.begin(), v.end());
+      HIPCHK(hipMemcpyAsync(d, c.data(), c.size() * sizeof(T), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    return d;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+};
+
+template <typename T>
+struct DevLevel {
+  LevelArgs a{};
+  const double* verts = nullptr;  // shared FP64 vertices
+  T* nu_q = nullptr;
+  T nu_const = 1;
+  T* tab = nullptr;
+  T *As_inv = nullptr, *Bm = nullptr, *F = nullptr, *Hinv = nullptr, *coef = nullptr, *dense = nullptr;
+  T *b = nullptr, *x = nullptr, *r = nullptr;
+  int64_t ndofs = 0;
+};
+
+template <typename T>
+struct DevTransfer {
+  TransferDev t{};
+  T *P1 = nullptr, *P1T = nullptr, *E = nullptr, *Pt = nullptr;
+  int *rlo = nullptr, *rhi = nullptr, *clo = nullptr, *chi = nullptr;
+  T *tmp1 = nullptr, *tmp2 = nullptr, *tmp3 = nullptr;
+};
+
+template <typename T>
+struct Hier {
+  std::vector<DevLevel<T>> L;
+  std::vector<DevTransfer<T>> X;
+};
+
+struct EventTimer {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pairs;
+  size_t used = 0;
+  hipEvent_t a(hipStream_t s) {
+    if (used == pairs.size()) {
+      hipEvent_t e1, e2;
+      HIPCHK(hipEventCreate(&e1));
+      HIPCHK(hipEventCreate(&e2));
+      pairs.push_back({e1, e2});
+    }
+    HIPCHK(hipEventRecord(pairs[used].first, s));
+    return pairs[used].first;
+  }
+  void b(hipStream_t s) {
+    HIPCHK(hipEventRecord(pairs[used].second, s));
+    ++used;
+  }
+  double total_s() {
+    double t = 0;
+    for (size_t i = 0; i < used; ++i) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, pairs[i].first, pairs[i].second));
+      t += ms * 1e-3;
+    }
+    return t;
+  }
+  void reset() { used = 0; }
+  ~EventTimer() {
+    for (auto& p : pairs) {
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+  }
+};
+
+}  // namespace
+
+struct stmg_ctx {
+  stmg_params p{};
+  std::string err;
+  hipStream_t stream = nullptr;
+  Pool pool;
+  std::vector<LevelHost> host;
+  std::vector<double*> verts;
+  // FP64 view of every level (operator, per-op calls); FP32 hierarchy in mixed mode
+  Hier<double> H64;
+  Hier<float> H32;
+  bool mixed = false;
+  double* Cinv = nullptr;
+  int64_t nd_coarse = 0;
+  double* mom0 = nullptr;  // finest-level pressure moments
+  double volume0 = 1.0;
+  // FGMRES work
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *partial = nullptr, *dh = nullptr, *dtmp = nullptr;
+  int cap = 0;
+  std::vector<double> history;
+  bool phase_timing = false;
+  EventTimer t_smooth, t_vcyc, t_op;
+};
+
+namespace {
+
+LevelArgs level_args(const LevelHost& L) {
+  LevelArgs a;
+  a.d = L.d; a.n = L.n; a.q = L.q; a.Q = L.Q; a.nn = L.nn; a.nt = L.nt; a.C = L.C; a.N = L.N; a.nloc = L.nloc;
+  a.nodes = L.nodes; a.Mv = L.Mv; a.Mp = L.Mp; a.slab = L.slab;
+  return a;
+}
+
+std::vector<double> pack_tables(const LevelHost& L) {
+  std::vector<double> t;
+  const SpaceTables& S = L.st;
+  t.insert(t.end(), S.S.begin(), S.S.end());
+  t.insert(t.end(), S.Dg.begin(), S.Dg.end());
+  t.insert(t.end(), S.gx.begin(), S.gx.end());
+  t.insert(t.end(), S.gw.begin(), S.gw.end());
+  t.insert(t.end(), L.td.K.begin(), L.td.K.end());
+  t.insert(t.end(), L.td.phim1.begin(), L.td.phim1.end());
+  for (int a = 0; a < L.nt; ++a) t.push_back(0.5 * L.tau * L.td.w[a]);
+  t.insert(t.end(), S.psi.begin(), S.psi.end());
+  return t;
+}
+
+template <typename T>
+void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
+                const std::vector<std::vector<double>>& dense, bool with_vanka) {
+  hipStream_t s = c->stream;
+  const size_t nlev = c->host.size();
+  H.L.resize(nlev);
+  for (size_t l = 0; l < nlev; ++l) {
+    const LevelHost& L = c->host[l];
+    DevLevel<T>& D = H.L[l];
+    D.a = level_args(L);
+    D.verts = c->verts[l];
+    D.nu_const = (T)L.nu_const;
+    if (!L.nu_q.empty()) D.nu_q = c->pool.upload<T>(L.nu_q, s);
+    D.tab = c->pool.upload<T>(pack_tables(L), s);
+    D.ndofs = L.ndofs;
+    D.b = c->pool.alloc<T>(L.ndofs);
+    D.x = c->pool.alloc<T>(L.ndofs);
+    D.r = c->pool.alloc<T>(L.ndofs);
+    if (with_vanka && l + 1 < nlev) {
+      const VankaFactors& V = VF[l];
+      D.coef = c->pool.upload<T>(V.coef, s);
+      if (c->p.vanka_mode == STMG_VANKA_DENSE) {
+        D.dense = c->pool.upload<T>(dense[l], s);
+      } else {
+        D.As_inv = c->pool.upload<T>(V.As_inv, s);
+        D.Bm = c->pool.upload<T>(V.Bm, s);
+        D.F = c->pool.upload<T>(V.F, s);
+        D.Hinv = c->pool.upload<T>(V.Hinv, s);
+      }
+    }
+  }
+  H.X.resize(nlev - 1);
+  for (size_t l = 0; l + 1 < nlev; ++l) {
+    const LevelHost& F = c->host[l];
+    const LevelHost& C = c->host[l + 1];
+    Transfer T0 = build_transfer(F, C);
+    DevTransfer<T>& X = H.X[l];
+    X.t.nnf = T0.nnf; X.t.nnc = T0.nnc; X.t.npos = T0.npos; X.t.ntf = T0.ntf; X.t.ntc = T0.ntc;
+    X.t.time_change = T0.time_change;
+    std::vector<double> P1T((size_t)T0.nnc * T0.nnf);
+    for (int g = 0; g < T0.nnf; ++g)
+      for (int h = 0; h < T0.nnc; ++h) P1T[(size_t)h * T0.nnf + g] = T0.P1[(size_t)g * T0.nnc + h];
+    X.P1 = c->pool.upload<T>(T0.P1, s);
+    X.P1T = c->pool.upload<T>(P1T, s);
+    X.rlo = c->pool.upload<int>(T0.row_lo, s);
+    X.rhi = c->pool.upload<int>(T0.row_hi, s);
+    X.clo = c->pool.upload<int>(T0.col_lo, s);
+    X.chi = c->pool.upload<int>(T0.col_hi, s);
+    X.E = c->pool.upload<T>(T0.E, s);
+    X.Pt = c->pool.upload<T>(T0.Pt, s);
+    // temporaries: batches of d-dimensional node arrays at fine time resolution
+    int64_t nb = (int64_t)F.N * F.nt * F.d;
+    int64_t big = std::max<int64_t>(F.nn, C.nn);
+    int64_t per = F.d == 3 ? big * big * big : big * big;
+    X.tmp1 = c->pool.alloc<T>(nb * per);
+    X.tmp2 = c->pool.alloc<T>(nb * per);
+    X.tmp3 = c->pool.alloc<T>((int64_t)F.N * F.nt * (C.Mv + C.Mp));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------- level ops
+template <typename T>
+void op_apply(stmg_ctx* c, DevLevel<T>& D, const T* x, const T* b, T* y, int mode) {
+  HIPCHK(launch_apply<T>(D.a, D.verts, D.nu_q, D.nu_const, D.tab, x, b, y, mode, c->stream));
+}
+
+template <typename T>
+void op_vanka(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x) {
+  T om = (T)c->p.omega;
+  if (c->p.vanka_mode == STMG_VANKA_DENSE)
+    HIPCHK(launch_vanka_dense<T>(D.a, D.dense, r, x, om, c->stream));
+  else
+    HIPCHK(launch_vanka_factored<T>(D.a, D.As_inv, D.Bm, D.F, D.Hinv, D.coef, r, x, om, c->stream));
+}
+
+template <typename T>
+void op_smooth(stmg_ctx* c, DevLevel<T>& D, const T* b, T* x, int steps, bool zero_start) {
+  for (int s = 0; s < steps; ++s) {
+    const T* r = b;
+    if (!(zero_start && s == 0)) {
+      op_apply<T>(c, D, x, b, D.r, 1);
+      r = D.r;
+    }
+    if (c->phase_timing) c->t_smooth.a(c->stream);
+    op_vanka<T>(c, D, r, x);
+    if (c->phase_timing) c->t_smooth.b(c->stream);
+  }
+}
+
+template <typename T>
+void op_restrict(stmg_ctx* c, Hier<T>& H, int l, const T* fine, T* coarse) {
+  DevTransfer<T>& X = H.X[l];
+  HIPCHK(launch_restrict<T>(H.L[l].a, H.L[l + 1].a, X.t, X.P1T, X.clo, X.chi, X.E, X.Pt, fine, coarse, X.tmp1,
+                            X.tmp2, X.tmp3, c->stream));
+}
+
+template <typename T>
+void op_prolongate_add(stmg_ctx* c, Hier<T>& H, int l, const T* coarse, T* fine) {
+  DevTransfer<T>& X = H.X[l];
+  HIPCHK(launch_prolongate_add<T>(H.L[l].a, H.L[l + 1].a, X.t, X.P1, X.rlo, X.rhi, X.E, X.Pt, coarse, fine, X.tmp1,
+                                  X.tmp2, X.tmp3, c->stream));
+}
+
+// x_l = V(b_l) on level l (zero initial guess), Alg. 1.
+template <typename T>
+void vcycle(stmg_ctx* c, Hier<T>& H, int l) {
+  DevLevel<T>& D = H.L[l];
+  const int last = (int)H.L.size() - 1;
+  if (l == last) {
+    HIPCHK(launch_coarse<T>(c->nd_coarse, c->Cinv, D.b, D.x, c->stream));
+    return;
+  }
+  HIPCHK(launch_fill<T>(D.x, T(0), D.ndofs, c->stream));
+  op_smooth<T>(c, D, D.b, D.x, c->p.nu_pre, true);                       // presmoothing
+  op_apply<T>(c, D, D.x, D.b, D.r, 1);                                   // residual
+  op_restrict<T>(c, H, l, D.r, H.L[l + 1].b);                            // restriction
+  vcycle<T>(c, H, l + 1);                                                // coarse-grid correction
+  op_prolongate_add<T>(c, H, l, H.L[l + 1].x, D.x);                      // prolongation and correction
+  op_smooth<T>(c, D, D.b, D.x, c->p.nu_post, false);                     // postsmoothing
+}
+
+// z = V(v) for FP64 vectors v, z (device), in the context's precision
+void precondition(stmg_ctx* c, const double* v, double* z) {
+  if (c->phase_timing) c->t_vcyc.a(c->stream);
+  if (c->mixed) {
+    DevLevel<float>& D = c->H32.L[0];
+    HIPCHK(launch_cast_d2f(v, D.b, D.ndofs, c->stream));
+    vcycle<float>(c, c->H32, 0);
+    HIPCHK(launch_cast_f2d(D.x, z, D.ndofs, c->stream));
+  } else {
+    DevLevel<double>& D = c->H64.L[0];
+    HIPCHK(hipMemcpyAsync(D.b, v, D.ndofs * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    vcycle<double>(c, c->H64, 0);
+    HIPCHK(hipMemcpyAsync(z, D.x, D.ndofs * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  }
+  if (c->phase_timing) c->t_vcyc.b(c->stream);
+}
+
+int fail(stmg_ctx* c, int code, const std::string& m) {
+  if (c) c->err = m;
+  return code;
+}
+
+template <typename F>
+int guarded(stmg_ctx* c, F&& f) {
+  try {
+    if (c) HIPCHK(hipSetDevice(c->p.device));
+    f();
+    return STMG_OK;
+  } catch (const Error& e) {
+    return fail(c, e.code, e.what());
+  } catch (const DeviceError& e) {
+    return fail(c, STMG_EDEVICE, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(c, STMG_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(c, STMG_EINVAL, e.what());
+  }
+}
+
+double dot(stmg_ctx* c, const double* a, const double* b, int64_t n) {
+  HIPCHK(launch_multidot(a, n, 1, b, n, c->partial, c->dh, c->stream));
+  double h;
+  HIPCHK(hipMemcpyAsync(&h, c->dh, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return h;
+}
+
+bool valid_pow2(int v) { return v >= 1 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+// Run a level operation in the context's precision on FP64 user vectors.
+template <typename F64, typename F32>
+static int per_op(stmg_ctx* c, F64&& f64, F32&& f32) {
+  return guarded(c, [&] {
+    if (c->mixed) f32();
+    else f64();
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+// ======================================================================= ABI
+extern "C" {
+
+stmg_status stmg_default_params(stmg_params* p) {
+  if (!p) return STMG_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->dim = 3; p->n_cells_1d = 4; p->n_coarse_1d = 2; p->deform_amp = 0.0;
+  p->r = 1; p->k = 1; p->n_sub = 2; p->tau = 0.05; p->nu = 1.0;
+  p->r_min = 1; p->k_min = 1; p->time_h_coarsening = 1; p->nu_pre = 1; p->nu_post = 1; p->omega = 0.8;
+  p->precision = STMG_FP64; p->vanka_mode = STMG_VANKA_FACTORED; p->device = 0; p->stream = nullptr;
+  return STMG_OK;
+}
+
+static int check_params(const stmg_params* p, std::string& msg) {
+  if (!p) { msg = "null params"; return STMG_EINVAL; }
+  if (p->dim != 2 && p->dim != 3) { msg = "dim must be 2 or 3"; return STMG_EINVAL; }
+  if (!valid_pow2(p->n_cells_1d) || !valid_pow2(p->n_coarse_1d) || p->n_coarse_1d > p->n_cells_1d) {
+    msg = "n_cells_1d and n_coarse_1d must be powers of two with n_coarse_1d <= n_cells_1d"; return STMG_EINVAL;
+  }
+  if (!valid_pow2(p->n_sub) || p->n_sub > 8) { msg = "n_sub must be 1, 2, 4 or 8"; return STMG_EINVAL; }
+  if (p->r < 1 || p->r > 2 || p->r_min < 1 || p->r_min > p->r) { msg = "supported: 1 <= r_min <= r <= 2"; return STMG_EUNSUPPORTED; }
+  if (p->k < 0 || p->k > 3 || p->k_min < 0 || p->k_min > p->k) { msg = "supported: 0 <= k_min <= k <= 3"; return STMG_EUNSUPPORTED; }
+  if (!(p->tau > 0) || !(p->nu > 0 || p->nu_fn)) { msg = "tau and nu must be positive"; return STMG_EINVAL; }
+  if (!(p->omega > 0) || p->nu_pre < 0 || p->nu_post < 0) { msg = "bad smoother parameters"; return STMG_EINVAL; }
+  if (p->precision != STMG_FP64 && p->precision != STMG_MIXED_FP32) { msg = "bad precision"; return STMG_EINVAL; }
+  if (p->vanka_mode != STMG_VANKA_FACTORED && p->vanka_mode != STMG_VANKA_DENSE) { msg = "bad vanka_mode"; return STMG_EINVAL; }
+  return STMG_OK;
+}
+
+stmg_status stmg_hierarchy(const stmg_params* p, int max_levels, int* levels_out, int* n_levels) {
+  std::string msg;
+  int e = check_params(p, msg);
+  if (e) return (stmg_status)e;
+  if (!levels_out || !n_levels) return STMG_EINVAL;
+  auto L = build_levels(p->n_cells_1d, p->r, p->k, p->n_sub, p->n_coarse_1d, p->r_min, p->k_min,
+                        p->time_h_coarsening != 0);
+  *n_levels = (int)L.size();
+  for (int i = 0; i < (int)L.size() && i < max_levels; ++i) {
+    levels_out[4 * i + 0] = L[i].n; levels_out[4 * i + 1] = L[i].r;
+    levels_out[4 * i + 2] = L[i].k; levels_out[4 * i + 3] = L[i].N;
+  }
+  return STMG_OK;
+}
+
+stmg_status stmg_setup(const stmg_params* p, stmg_ctx** out) {
+  if (!out) return STMG_EINVAL;
+  *out = nullptr;
+  std::string msg;
+  int e = check_params(p, msg);
+  if (e) return (stmg_status)e;
+  auto* c = new (std::nothrow) stmg_ctx();
+  if (!c) return STMG_ENOMEM;
+  c->p = *p;
+  c->mixed = p->precision == STMG_MIXED_FP32;
+  int rc = guarded(c, [&] {
+    c->stream = static_cast<hipStream_t>(p->stream);
+    Params P;
+    P.d = p->dim; P.n = p->n_cells_1d; P.n_coarse = p->n_coarse_1d; P.r = p->r; P.k = p->k; P.N = p->n_sub;
+    P.r_min = p->r_min; P.k_min = p->k_min; P.time_h = p->time_h_coarsening != 0;
+    P.amp = p->deform_amp; P.tau = p->tau; P.nu = p->nu;
+    if (p->nu_fn) {
+      stmg_nu_fn fn = p->nu_fn;
+      void* user = p->nu_user;
+      P.nu_fn = [fn, user](int n, const double* xyz, double* o) { fn(n, xyz, o, user); };
+    }
+    auto specs = build_levels(P.n, P.r, P.k, P.N, P.n_coarse, P.r_min, P.k_min, P.time_h);
+    int nthreads = 1;
+#ifdef _OPENMP
+    nthreads = omp_get_max_threads();
+#endif
+    c->host.resize(specs.size());
+    for (size_t l = 0; l < specs.size(); ++l) build_level(P, specs[l], c->host[l]);
+    std::vector<VankaFactors> VF(specs.size());
+    std::vector<std::vector<double>> dense(specs.size());
+    for (size_t l = 0; l + 1 < specs.size(); ++l) {
+      vanka_factors(c->host[l], VF[l], nthreads);
+      if (p->vanka_mode == STMG_VANKA_DENSE) vanka_dense(c->host[l], VF[l], dense[l], nthreads);
+    }
+    std::vector<double> cinv;
+    coarse_inverse(c->host.back(), cinv);
+    c->nd_coarse = c->host.back().ndofs;
+    for (auto& L : c->host) c->verts.push_back(c->pool.upload<double>(L.verts, c->stream));
+    c->Cinv = c->pool.upload<double>(cinv, c->stream);
+    c->mom0 = c->pool.upload<double>(c->host[0].mom, c->stream);
+    c->volume0 = c->host[0].volume;
+    // the FP64 hierarchy always exists (operator, per-op calls); it holds the
+    // smoother factors only in FP64 mode
+    build_hier<double>(c, c->H64, VF, dense, !c->mixed);
+    if (c->mixed) build_hier<float>(c, c->H32, VF, dense, true);
+    int64_t ns = (int64_t)c->host[0].N * c->host[0].nt;
+    c->partial = c->pool.alloc<double>((ns + 128) * 520 + 1024 * 128);
+    c->dh = c->pool.alloc<double>(1024);
+    c->w = c->pool.alloc<double>(c->host[0].ndofs);
+    c->dtmp = c->pool.alloc<double>(c->host[0].ndofs);
+    // release host element matrices (kept: level sizes and tables)
+    for (auto& L : c->host) {
+      std::vector<double>().swap(L.Me);
+      std::vector<double>().swap(L.Ae);
+      std::vector<double>().swap(L.Be);
+    }
+  });
+  if (rc != STMG_OK) {
+    std::string m = c->err;
+    c->pool.release();
+    delete c;
+    (void)m;
+    return (stmg_status)rc;
+  }
+  *out = c;
+  return STMG_OK;
+}
+
+stmg_status stmg_destroy(stmg_ctx* c) {
+  if (!c) return STMG_EINVAL;
+  (void)hipSetDevice(c->p.device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  c->pool.release();
+  delete c;
+  return STMG_OK;
+}
+
+const char* stmg_last_error(const stmg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+stmg_status stmg_sizes(const stmg_ctx* c, int level, int64_t* n_dofs, int64_t* nv, int64_t* np, int* n_levels) {
+  if (!c || level < 0 || level >= (int)c->host.size()) return STMG_EINVAL;
+  const LevelHost& L = c->host[level];
+  if (n_dofs) *n_dofs = L.ndofs;
+  if (nv) *nv = L.Mv;
+  if (np) *np = L.Mp;
+  if (n_levels) *n_levels = (int)c->host.size();
+  return STMG_OK;
+}
+
+stmg_status stmg_set_phase_timing(stmg_ctx* c, int on) {
+  if (!c) return STMG_EINVAL;
+  c->phase_timing = on != 0;
+  return STMG_OK;
+}
+
+stmg_status stmg_apply_operator(stmg_ctx* c, int level, const double* x, double* y) {
+  if (!c || !x || !y || level < 0 || level >= (int)c->host.size()) return STMG_EINVAL;
+  // the operator is always available in FP64 (the FGMRES operator)
+  return (stmg_status)guarded(c, [&] {
+    op_apply<double>(c, c->H64.L[level], x, x, y, 0);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+stmg_status stmg_residual(stmg_ctx* c, int level, const double* b, const double* x, double* r) {
+  if (!c || !b || !x || !r || level < 0 || level >= (int)c->host.size()) return STMG_EINVAL;
+  return (stmg_status)guarded(c, [&] {
+    op_apply<double>(c, c->H64.L[level], x, b, r, 1);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+stmg_status stmg_smooth(stmg_ctx* c, int level, const double* b, double* x, int steps) {
+  if (!c || !b || !x || level < 0 || level + 1 >= (int)c->host.size() || steps < 0) return STMG_EINVAL;
+  return (stmg_status)per_op(
+      c, [&] { op_smooth<double>(c, c->H64.L[level], b, x, steps, false); },
+      [&] {
+        DevLevel<float>& D = c->H32.L[level];
+        HIPCHK(launch_cast_d2f(b, D.b, D.ndofs, c->stream));
+        HIPCHK(launch_cast_d2f(x, D.x, D.ndofs, c->stream));
+        op_smooth<float>(c, D, D.b, D.x, steps, false);
+        HIPCHK(launch_cast_f2d(D.x, x, D.ndofs, c->stream));
+      });
+}
+
+stmg_status stmg_vanka_correction(stmg_ctx* c, int level, const double* r, double* x) {
+  if (!c || !r || !x || level < 0 || level + 1 >= (int)c->host.size()) return STMG_EINVAL;
+  return (stmg_status)per_op(
+      c, [&] { op_vanka<double>(c, c->H64.L[level], r, x); },
+      [&] {
+        DevLevel<float>& D = c->H32.L[level];
+        HIPCHK(launch_cast_d2f(r, D.r, D.ndofs, c->stream));
+        HIPCHK(launch_cast_d2f(x, D.x, D.ndofs, c->stream));
+        op_vanka<float>(c, D, D.r, D.x);
+        HIPCHK(launch_cast_f2d(D.x, x, D.ndofs, c->stream));
+      });
+}
+
+stmg_status stmg_kernel_time(stmg_ctx* c, int which, int level, int reps, double* avg_ms) {
+  if (!c || !avg_ms || reps < 1 || level < 0 || level >= (int)c->host.size()) return STMG_EINVAL;
+  if (which == 0 && level + 1 >= (int)c->host.size()) return STMG_EINVAL;
+  if (which != 0 && which != 1) return STMG_EINVAL;
+  return (stmg_status)guarded(c, [&] {
+    auto run = [&](auto& D) {
+      using T = std::remove_reference_t<decltype(*D.x)>;
+      HIPCHK(launch_fill<T>(D.b, T(1e-3), D.ndofs, c->stream));
+      HIPCHK(launch_fill<T>(D.x, T(0), D.ndofs, c->stream));
+      HIPCHK(launch_fill<T>(D.r, T(1e-3), D.ndofs, c->stream));
+      hipEvent_t e0, e1;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      HIPCHK(hipEventRecord(e0, c->stream));
+      for (int i = 0; i < reps; ++i) {
+        if (which == 0) op_vanka<T>(c, D, D.r, D.x);
+        else op_apply<T>(c, D, D.x, D.b, D.r, 1);
+      }
+      HIPCHK(hipEventRecord(e1, c->stream));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      *avg_ms = ms / reps;
+    };
+    if (c->mixed && which == 0) run(c->H32.L[level]);
+    else if (c->mixed) run(c->H32.L[level]);
+    else run(c->H64.L[level]);
+  });
+}
+
+stmg_status stmg_restrict(stmg_ctx* c, int level, const double* fine, double* coarse) {
+  if (!c || !fine || !coarse || level < 0 || level + 1 >= (int)c->host.size()) return STMG_EINVAL;
+  return (stmg_status)per_op(
+      c, [&] { op_restrict<double>(c, c->H64, level, fine, coarse); },
+      [&] {
+        DevLevel<float>& F = c->H32.L[level];
+        DevLevel<float>& C = c->H32.L[level + 1];
+        HIPCHK(launch_cast_d2f(fine, F.r, F.ndofs, c->stream));
+        op_restrict<float>(c, c->H32, level, F.r, C.b);
+        HIPCHK(launch_cast_f2d(C.b, coarse, C.ndofs, c->stream));
+      });
+}
+
+stmg_status stmg_prolongate(stmg_ctx* c, int level, const double* coarse, double* fine) {
+  if (!c || !fine || !coarse || level < 0 || level + 1 >= (int)c->host.size()) return STMG_EINVAL;
+  return (stmg_status)per_op(
+      c,
+      [&] {
+        HIPCHK(launch_fill<double>(fine, 0.0, c->host[level].ndofs, c->stream));
+        op_prolongate_add<double>(c, c->H64, level, coarse, fine);
+      },
+      [&] {
+        DevLevel<float>& F = c->H32.L[level];
+        DevLevel<float>& C = c->H32.L[level + 1];
+        HIPCHK(launch_cast_d2f(coarse, C.x, C.ndofs, c->stream));
+        HIPCHK(launch_fill<float>(F.x, 0.0f, F.ndofs, c->stream));
+        op_prolongate_add<float>(c, c->H32, level, C.x, F.x);
+        HIPCHK(launch_cast_f2d(F.x, fine, F.ndofs, c->stream));
+      });
+}
+
+stmg_status stmg_coarse_solve(stmg_ctx* c, const double* b, double* x) {
+  if (!c || !b || !x) return STMG_EINVAL;
+  return (stmg_status)guarded(c, [&] {
+    HIPCHK(launch_coarse<double>(c->nd_coarse, c->Cinv, b, x, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+stmg_status stmg_vcycle(stmg_ctx* c, const double* b, double* x) {
+  if (!c || !b || !x) return STMG_EINVAL;
+  return (stmg_status)guarded(c, [&] {
+    precondition(c, b, x);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+stmg_status stmg_project_pressure_mean_zero(stmg_ctx* c, double* x) {
+  if (!c || !x) return STMG_EINVAL;
+  return (stmg_status)guarded(c, [&] {
+    HIPCHK(launch_project_pressure(c->H64.L[0].a, c->mom0, c->volume0, x, c->partial, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int max_it, stmg_solve_info* info) {
+  if (!c || !b || !x || !(rtol > 0) || max_it < 1) return STMG_EINVAL;
+  int status = STMG_OK;
+  int rc = guarded(c, [&] {
+    const int64_t n = c->host[0].ndofs;
+    hipStream_t s = c->stream;
+    DevLevel<double>& L0 = c->H64.L[0];
+    // Krylov basis capacity: bounded by max_it and by free device memory
+    int want = std::min(max_it, 100) + 1;
+    if (c->cap < want) {
+      size_t fr = 0, tot = 0;
+      HIPCHK(hipMemGetInfo(&fr, &tot));
+      int64_t fit = (int64_t)(0.45 * (double)fr / (2.0 * n * sizeof(double)));
+      int cap = (int)std::max<int64_t>(8, std::min<int64_t>(want, fit));
+      if (cap > c->cap) {
+        if (c->V) { (void)hipFree(c->V); (void)hipFree(c->Z); }
+        c->V = nullptr;
+        c->Z = nullptr;
+        HIPCHK(hipMalloc(&c->V, (size_t)cap * n * sizeof(double)));
+        HIPCHK(hipMalloc(&c->Z, (size_t)cap * n * sizeof(double)));
+        c->cap = cap;
+      }
+    }
+    const int m = c->cap - 1;
+    c->history.clear();
+    c->t_smooth.reset();
+    c->t_vcyc.reset();
+    c->t_op.reset();
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+    HIPCHK(launch_fill<double>(x, 0.0, n, s));
+    double bnorm = std::sqrt(dot(c, b, b, n));
+    int total = 0;
+    double rel = 0.0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hv(m + 2), y(m);
+    while (true) {
+      // explicit residual
+      if (c->phase_timing) c->t_op.a(s);
+      op_apply<double>(c, L0, x, b, c->w, 1);
+      if (c->phase_timing) c->t_op.b(s);
+      double beta = std::sqrt(dot(c, c->w, c->w, n));
+      rel = bnorm > 0 ? beta / bnorm : 0.0;
+      c->history.push_back(rel);
+      if (bnorm == 0.0 || beta <= rtol * bnorm || total >= max_it) break;
+      HIPCHK(launch_scale_copy(c->V, c->w, 1.0 / beta, n, s));
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int j = 0;
+      while (j < m && total < max_it) {
+        double* vj = c->V + (size_t)j * n;
+        double* zj = c->Z + (size_t)j * n;
+        precondition(c, vj, zj);
+        double* wv = c->V + (size_t)(j + 1) * n;
+        if (c->phase_timing) c->t_op.a(s);
+        op_apply<double>(c, L0, zj, zj, wv, 0);
+        if (c->phase_timing) c->t_op.b(s);
+        // CGS2
+        std::fill(hv.begin(), hv.end(), 0.0);
+        for (int pass = 0; pass < 2; ++pass) {
+          HIPCHK(launch_multidot(c->V, n, j + 1, wv, n, c->partial, c->dh, s));
+          HIPCHK(launch_multi_axpy(wv, c->V, n, j + 1, c->dh, n, s));
+          std::vector<double> hh(j + 1);
+          HIPCHK(hipMemcpyAsync(hh.data(), c->dh, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+          HIPCHK(hipStreamSynchronize(s));
+          for (int i = 0; i <= j; ++i) hv[i] += hh[i];
+        }
+        double hn = std::sqrt(dot(c, wv, wv, n));
+        hv[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {
+          double t = cs[i] * hv[i] + sn[i] * hv[i + 1];
+          hv[i + 1] = -sn[i] * hv[i] + cs[i] * hv[i + 1];
+          hv[i] = t;
+        }
+        double den = std::hypot(hv[j], hv[j + 1]);
+        cs[j] = hv[j] / den;
+        sn[j] = hv[j + 1] / den;
+        hv[j] = den;
+        hv[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        for (int i = 0; i <= j + 1; ++i) H[(size_t)i * m + j] = hv[i];
+        ++total;
+        ++j;
+        c->history.push_back(std::fabs(g[j]) / bnorm);
+        if (!std::isfinite(g[j])) throw Error(STMG_ESINGULAR, "FGMRES produced a non-finite residual");
+        if (std::fabs(g[j]) <= rtol * bnorm || hn == 0.0) break;
+        HIPCHK(launch_scale_copy(wv, wv, 1.0 / hn, n, s));
+      }
+      for (int i = j - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int k2 = i + 1; k2 < j; ++k2) t -= H[(size_t)i * m + k2] * y[k2];
+        y[i] = t / H[(size_t)i * m + i];
+      }
+      HIPCHK(hipMemcpyAsync(c->dh, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
+      HIPCHK(launch_combine(x, c->Z, n, j, c->dh, n, s));
+    }
+    HIPCHK(launch_project_pressure(L0.a, c->mom0, c->volume0, x, c->partial, s));
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->iterations = total;
+      info->rel_residual = rel;
+      info->t_solve_s = ms * 1e-3;
+      if (c->phase_timing) {
+        info->t_smoother_s = c->t_smooth.total_s();
+        double tv = c->t_vcyc.total_s();
+        info->t_mg_other_s = tv - info->t_smoother_s;
+        info->t_operator_s = c->t_op.total_s();
+        info->t_other_s = info->t_solve_s - tv - info->t_operator_s;
+      }
+      info->history_len = (int)c->history.size();
+      info->history = c->history.data();
+    }
+    if (!(rel <= rtol)) status = STMG_ENOCONV;
+  });
+  if (rc != STMG_OK) return (stmg_status)rc;
+  if (status != STMG_OK) c->err = "FGMRES did not reach the tolerance within max_it";
+  return (stmg_status)status;
+}
+
+}  // extern "C"

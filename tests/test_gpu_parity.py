@@ -1,0 +1,193 @@
+"""GPU parity: every step of the hot path, called through the C ABI, against
+the CPU oracle on the same seeded inputs.  FP64 tolerance 1e-12 relative
+(max-norm) for the operator, smoother, transfers and coarse solve; identical
+FGMRES iteration counts; solutions within 1e-10 after the per-slice pressure
+projection."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import CONFIGS, announce, dev, host, make_solver, oracle_mg, rel, rhs
+
+pytestmark = pytest.mark.gpu
+
+NAMES = list(CONFIGS)
+_solvers = {}
+
+
+def solver(name, **over):
+    key = (name, tuple(sorted(over.items())))
+    if key not in _solvers:
+        announce(f"setup {name} {over}")
+        _solvers[key] = make_solver(CONFIGS[name], **over)
+    return _solvers[key]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cleanup():
+    yield
+    for s in _solvers.values():
+        s.close()
+    _solvers.clear()
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_level_sizes_match(name):
+    g, o = solver(name), oracle_mg(name)
+    assert g.n_levels == len(o.levels)
+    for l, L in enumerate(o.levels):
+        nd, nv, npr, _ = g.sizes(l)
+        assert (nd, nv, npr) == (L.ndofs, L.Mv, L.Mp)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_apply_every_level(name):
+    """Eq. (GloSys): matrix-free apply = assembled mat-vec, <= 1e-12."""
+    g, o = solver(name), oracle_mg(name)
+    rng = np.random.default_rng(11)
+    for l, L in enumerate(o.levels):
+        announce(f"apply {name} level {l}")
+        x = rng.standard_normal(L.ndofs)
+        y = torch.empty(L.ndofs, dtype=torch.float64, device="cuda")
+        g.apply(dev(x), y, level=l)
+        ref = L.csr() @ x
+        assert rel(host(y), ref) < 1e-12, (l, rel(host(y), ref))
+        b = rng.standard_normal(L.ndofs)
+        r = torch.empty_like(y)
+        g.residual(dev(b), dev(x), r, level=l)
+        assert rel(host(r), b - ref) < 1e-12
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_smoother_every_level(name):
+    """Eq. (vanka): one and two cell-Vanka sweeps, <= 1e-12."""
+    g, o = solver(name), oracle_mg(name)
+    rng = np.random.default_rng(12)
+    for l, L in enumerate(o.levels[:-1]):
+        announce(f"smooth {name} level {l}")
+        dm = L.dirichlet_mask()
+        b = rng.standard_normal(L.ndofs); b[dm] = 0
+        x0 = rng.standard_normal(L.ndofs); x0[dm] = 0
+        for steps in (1, 2):
+            xg = dev(x0)
+            g.smooth(dev(b), xg, steps=steps, level=l)
+            ref = o.smoothers[l].smooth(b, x0.copy(), steps, L.apply)
+            assert rel(host(xg), ref) < 1e-12, (l, steps, rel(host(xg), ref))
+
+
+def test_dense_and_factored_vanka_agree():
+    """The dense local inverse and its Schur-factored form give the same sweep."""
+    name = "c2_small"
+    gf, gd = solver(name), solver(name, vanka_mode=1)
+    o = oracle_mg(name)
+    rng = np.random.default_rng(13)
+    for l, L in enumerate(o.levels[:-1]):
+        dm = L.dirichlet_mask()
+        b = rng.standard_normal(L.ndofs); b[dm] = 0
+        x1, x2 = dev(np.zeros(L.ndofs)), dev(np.zeros(L.ndofs))
+        gf.smooth(dev(b), x1, 1, level=l)
+        gd.smooth(dev(b), x2, 1, level=l)
+        assert rel(host(x2), host(x1)) < 1e-12
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_transfers_every_pair(name):
+    """App. A: prolongation P and restriction P^T, <= 1e-12."""
+    g, o = solver(name), oracle_mg(name)
+    rng = np.random.default_rng(14)
+    for l, P in enumerate(o.P):
+        announce(f"transfer {name} pair {l}")
+        xc = rng.standard_normal(P.shape[1])
+        xf = torch.empty(P.shape[0], dtype=torch.float64, device="cuda")
+        g.prolongate(dev(xc), xf, level=l)
+        assert rel(host(xf), P @ xc) < 1e-12
+        rf = rng.standard_normal(P.shape[0])
+        bc = torch.empty(P.shape[1], dtype=torch.float64, device="cuda")
+        g.restrict(dev(rf), bc, level=l)
+        assert rel(host(bc), P.T @ rf) < 1e-12
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_coarse_solve(name):
+    """Alg. 1 step 3: bordered direct solve, mean-zero pressure."""
+    g, o = solver(name), oracle_mg(name)
+    L = o.levels[-1]
+    rng = np.random.default_rng(15)
+    b = rng.standard_normal(L.ndofs)
+    x = torch.empty(L.ndofs, dtype=torch.float64, device="cuda")
+    g.coarse_solve(dev(b), x)
+    assert rel(host(x), o.coarse.solve(b)) < 1e-11
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_vcycle(name):
+    """Alg. 1: one V-cycle from zero."""
+    g, o = solver(name), oracle_mg(name)
+    b = rhs(CONFIGS[name], 21)
+    x = torch.empty(len(b), dtype=torch.float64, device="cuda")
+    g.vcycle(dev(b), x)
+    assert rel(host(x), o.vcycle(b)) < 1e-11
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_solve_iterations_and_solution(name):
+    """FGMRES + V-cycle: identical iteration counts, solution within 1e-10."""
+    from oracle.fgmres import fgmres
+    g, o = solver(name), oracle_mg(name)
+    L = o.levels[0]
+    b = rhs(CONFIGS[name], 22)
+    for rtol in (1e-8, 1e-10):
+        x = torch.empty(len(b), dtype=torch.float64, device="cuda")
+        info = g.solve(dev(b), x, rtol=rtol, max_it=100)
+        xo, it, hist = fgmres(L.apply, o.vcycle, b, rtol=rtol, max_it=100)
+        announce(f"solve {name} rtol {rtol}: gpu {info['iterations']} oracle {it}")
+        assert info["iterations"] == it
+        assert info["rel_residual"] <= rtol
+        xo = L.project_pressure(xo)
+        assert np.linalg.norm(host(x) - xo) / np.linalg.norm(xo) < 100 * rtol
+        if rtol == 1e-10:
+            assert np.linalg.norm(host(x) - xo) / np.linalg.norm(xo) < 1e-10
+
+
+def test_c1_manufactured_solution():
+    """C1 (2D, 840 dofs, manufactured forcing assembled by the oracle), FGMRES
+    to 1e-10: equals the oracle's bordered direct solve."""
+    from oracle.coarse import CoarseSolver
+    from oracle.errors import load_vector
+    from stmg_inputs import Manufactured2D
+    g, o = solver("c1"), oracle_mg("c1")
+    L = o.levels[0]
+    b = load_vector(L, Manufactured2D(1.0).f)
+    x = torch.empty(L.ndofs, dtype=torch.float64, device="cuda")
+    info = g.solve(dev(b), x, rtol=1e-10)
+    xd = CoarseSolver(L).solve(b)
+    assert info["rel_residual"] <= 1e-10
+    assert np.linalg.norm(host(x) - xd) / np.linalg.norm(xd) < 1e-9
+
+
+@pytest.mark.parametrize("name", ["c2_small", "c5_small"])
+def test_mixed_precision_solution(name):
+    """FP32 V-cycle inside FP64 FGMRES: converges to the same solution
+    (within 1e-8 of the FP64 solution when both are solved to 1e-10)."""
+    g64 = solver(name)
+    g32 = solver(name, precision=1)
+    b = dev(rhs(CONFIGS[name], 23))
+    x64 = torch.empty_like(b)
+    x32 = torch.empty_like(b)
+    i64 = g64.solve(b, x64, rtol=1e-10)
+    i32 = g32.solve(b, x32, rtol=1e-10)
+    announce(f"mixed {name}: fp64 {i64['iterations']} it, fp32 {i32['iterations']} it")
+    assert i32["rel_residual"] <= 1e-10
+    err = (torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64)).item()
+    assert err < 1e-8, err
+    assert i32["iterations"] <= i64["iterations"] + 3
+
+
+def test_pressure_projection():
+    from gpu_common import oracle_mg as om
+    g, o = solver("c5_small"), om("c5_small")
+    L = o.levels[0]
+    x = np.random.default_rng(16).standard_normal(L.ndofs)
+    xg = dev(x)
+    g.project_pressure(xg)
+    assert rel(host(xg), L.project_pressure(x)) < 1e-12
