@@ -21,7 +21,7 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     # 3D Stokes, Q3/P2disc x DG(2), 16^3 deformed hexes, slab of 4 subintervals, hp MG k -> 0
-    "c2": dict(dim=3, n_cells_1d=16, n_coarse_1d=2, r=2, k=2, n_sub=4, deform_amp=0.03, k_min=0, seed=2,
+    "c2": dict(dim=3, n_cells_1d=16, n_coarse_1d=2, r=2, k=2, n_sub=4, deform_amp=0.03, k_min=2, seed=2,
                label="3D Stokes Q3/P2disc x DG(2), 16^3 deformed hex mesh, slab of 4 subintervals, nu=1"),
     # 3D Stokes, Q3/P2disc x DG(1), 32^3 deformed, 4 subintervals
     "c3": dict(dim=3, n_cells_1d=32, n_coarse_1d=2, r=2, k=1, n_sub=4, deform_amp=0.03, k_min=1, seed=3,
@@ -92,6 +92,7 @@ def main():
     ap.add_argument("--variant", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
+    ap.add_argument("--k-min", type=int, default=None, help="override the temporal p-coarsening floor")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (multi-GPU sharding is a design, not built)",
@@ -103,7 +104,9 @@ def main():
     from paper_2502_09159_amd import stmg
     from stmg_inputs import FourierViscosity, random_rhs
 
-    w = WORKLOADS[args.workload]
+    w = dict(WORKLOADS[args.workload])
+    if args.k_min is not None:
+        w["k_min"] = args.k_min
     nu_fn = FourierViscosity(w["nu_seed"]) if "nu_seed" in w else None
     prec = stmg.MIXED_FP32 if args.variant == "mixed" else stmg.FP64
     t0 = time.perf_counter()

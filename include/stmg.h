@@ -80,7 +80,10 @@ typedef struct {
   stmg_nu_fn nu_fn;      /* optional nu(x) */
   void* nu_user;
   int r_min, k_min;      /* p-coarsening floors (>= 1 and >= 0) */
-  int time_h_coarsening; /* 1: halve N on the coarsest spatial h-steps */
+  int time_h_coarsening; /* 1: also coarsen the slab in time (N -> N/2) */
+  int placement;         /* 0: Alg. 2 + Alg. 3 of Sec. 4.4 (temporal coarsening
+                            on the coarsest levels); 1: halve r and k together
+                            on the fine mesh first */
   int nu_pre, nu_post;   /* Vanka sweeps before/after the coarse correction */
   double omega;          /* Vanka relaxation */
   int precision;         /* stmg_precision */
@@ -90,8 +93,8 @@ typedef struct {
 } stmg_params;
 
 /* Fill p with the defaults (3D, n=4, r=1, k=1, N=2, tau=0.05, nu=1,
- * r_min=k_min=1, time h-coarsening on, one pre/post sweep, omega=0.8, FP64,
- * factored Vanka, device 0, default stream). */
+ * r_min=k_min=1, no temporal h-coarsening, placement 0, one pre/post sweep,
+ * omega=0.8, FP64, factored Vanka, device 0, default stream). */
 stmg_status stmg_default_params(stmg_params* p);
 
 /* Build the level list of the hp hierarchy without touching a GPU

@@ -6,9 +6,11 @@ N=subintervals).  Lists are returned finest first (index 0 = finest).
 * ``build_levels``: the build's default placement (reading G12): first halve r
   and k together on the fine mesh (p before h, principle P2 of Sec. 4.4;
   k -> floor(k/2) and r -> floor(r/2), Eq. (Assmp:MG2)), each floored at its
-  minimum; then halve the mesh size down to the coarsest mesh; temporal
-  h-coarsening N -> N/2 is aligned with the coarsest spatial h-steps
-  (space before time, P1; space-time coarsening at the coarse end, P3).
+  minimum; then halve the mesh size down to the coarsest mesh.  Optional
+  temporal h-coarsening N -> N/2 is aligned with the coarsest spatial h-steps
+  (space before time, P1; space-time coarsening at the coarse end, P3).  It
+  is off by default: on the slab workloads it costs iterations (a slab then
+  keeps all N subintervals down to the coarsest level, solved exactly).
 * ``construct_hierarchy`` / ``combine_hierarchies``: Alg. 2 and Alg. 3 as
   described in Sec. 4.4, used to check the worked example of App. C and the
   smoother sizes of Table 2(b).
@@ -16,7 +18,37 @@ N=subintervals).  Lists are returned finest first (index 0 = finest).
 from .elements import vanka_block_size
 
 
-def build_levels(n, r, k, N, n_coarse=1, r_min=1, k_min=1, time_h=True):
+def build_levels(n, r, k, N, n_coarse=1, r_min=1, k_min=1, time_h=False, placement="paper"):
+    """Level list, finest first, as dicts (n, r, k, N).
+
+    placement "paper" (default): Alg. 2 builds a spatial list (halve r on the
+    fine mesh down to r_min, then halve the mesh size down to n_coarse) and a
+    temporal list (halve k down to k_min, then, if time_h, halve N down to
+    1); Alg. 3 pads the shorter list at its fine end and pairs the lists
+    level by level, so temporal coarsening happens on the coarsest levels
+    (principles P3/P4 of Sec. 4.4, App. C).
+    placement "top": r and k are halved together on the fine mesh first
+    (kept for comparison; it converges poorly for k >= 1, see DESIGN)."""
+    if placement == "paper":
+        space = [(n, r)]
+        while r > r_min:
+            r = max(r // 2, r_min)
+            space.append((n, r))
+        while n > n_coarse:
+            n //= 2
+            space.append((n, r))
+        time = [(N, k)]
+        while k > k_min:
+            k = max(k // 2, k_min)
+            time.append((N, k))
+        if time_h:
+            while N > 1:
+                N //= 2
+                time.append((N, k))
+        L = max(len(space), len(time))
+        space = [space[0]] * (L - len(space)) + space
+        time = [time[0]] * (L - len(time)) + time
+        return [dict(n=a[0], r=a[1], k=b[1], N=b[0]) for a, b in zip(space, time)]
     levels = [dict(n=n, r=r, k=k, N=N)]
     while r > r_min or k > k_min:
         r = max(r // 2, r_min) if r > r_min else r

@@ -20,8 +20,9 @@ from .vanka import Vanka
 
 class Multigrid:
     def __init__(self, d, n, r, k, N, tau, nu=1.0, amp=0.0, n_coarse=1, r_min=1,
-                 k_min=1, time_h=True, omega=0.8, nu_pre=1, nu_post=1, literal=None):
-        self.spec = build_levels(n, r, k, N, n_coarse, r_min, k_min, time_h)
+                 k_min=1, time_h=False, omega=0.8, nu_pre=1, nu_post=1, literal=None,
+                 placement="paper"):
+        self.spec = build_levels(n, r, k, N, n_coarse, r_min, k_min, time_h, placement)
         spatial = {}
         self.levels = []
         for s in self.spec:

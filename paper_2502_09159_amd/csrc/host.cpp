@@ -185,10 +185,26 @@ SpaceTables space_tables(int d, int r) {
 
 // ---------------------------------------------------------------- levels
 std::vector<LevelSpec> build_levels(int n, int r, int k, int N, int n_coarse, int r_min, int k_min,
-                                    bool time_h) {
+                                    bool time_h, int placement) {
   std::vector<LevelSpec> L;
+  if (placement == 0) {
+    // Alg. 2 for space (p-halving on the fine mesh, then h) and for time
+    // (p-halving, then optional h), Alg. 3: pad the shorter list at its fine
+    // end and pair level by level -> temporal coarsening on the coarsest levels.
+    std::vector<std::pair<int, int>> sp{{n, r}}, tm{{N, k}};
+    while (r > r_min) { r = std::max(r / 2, r_min); sp.push_back({n, r}); }
+    while (n > n_coarse) { n /= 2; sp.push_back({n, r}); }
+    while (k > k_min) { k = std::max(k / 2, k_min); tm.push_back({N, k}); }
+    if (time_h)
+      while (N > 1) { N /= 2; tm.push_back({N, k}); }
+    size_t len = std::max(sp.size(), tm.size());
+    while (sp.size() < len) sp.insert(sp.begin(), sp.front());
+    while (tm.size() < len) tm.insert(tm.begin(), tm.front());
+    for (size_t i = 0; i < len; ++i) L.push_back({sp[i].first, sp[i].second, tm[i].second, tm[i].first});
+    return L;
+  }
+  // placement 1: halve r and k together on the fine mesh first, then h
   L.push_back({n, r, k, N});
-  // p-coarsening on the fine mesh: halve r and k together (floored)
   while (r > r_min || k > k_min) {
     if (r > r_min) r = std::max(r / 2, r_min);
     if (k > k_min) k = std::max(k / 2, k_min);
@@ -618,10 +634,9 @@ void vanka_dense(const LevelHost& L, const VankaFactors& V, std::vector<double>&
 }
 
 // ------------------------------------------------------------ coarse level
-void coarse_inverse(const LevelHost& L, std::vector<double>& inv) {
+void coarse_inverse(const LevelHost& L, std::vector<double>& Dinv, std::vector<double>& G) {
   const int d = L.d, nl = L.nloc, C = L.C, nt = L.nt;
-  const int64_t nd = L.ndofs;
-  const int ns = L.N * nt;
+  const int64_t nd = L.slab;  // one subinterval
   if (nd > 12000) throw Error(-1, "coarsest level too large for the dense bordered solve");
   const int64_t nn = L.nodes;
   // global scalar mass / Laplacian and divergence
@@ -651,47 +666,63 @@ void coarse_inverse(const LevelHost& L, std::vector<double>& inv) {
         for (int i = 0; i < nl; ++i)
           B[(size_t)(c * C + l) * L.Mv + a * nn + gn[i]] = L.Be[(((size_t)c * C + l) * d + a) * nl + i];
   }
-  const int64_t nb = nd + ns;
+  // one subinterval block D bordered with nt constraint rows/columns
+  const int64_t nb = nd + nt;
   std::vector<double> S((size_t)nb * nb, 0.0);  // column-major
   auto at = [&](int64_t row, int64_t col) -> double& { return S[(size_t)col * nb + row]; };
-  auto vidx = [&](int n, int a, int comp, int64_t node) { return n * L.slab + a * L.Mv + comp * nn + node; };
-  auto pidx = [&](int n, int a, int64_t p) { return n * L.slab + nt * L.Mv + a * L.Mp + p; };
-  for (int n = 0; n < L.N; ++n)
-    for (int a = 0; a < nt; ++a) {
-      double ca = 0.5 * L.tau * L.td.w[a];
-      for (int comp = 0; comp < d; ++comp)
-        for (int64_t i = 0; i < nn; ++i) {
-          int64_t row = vidx(n, a, comp, i);
-          if (bnd[i]) { at(row, row) = 1.0; continue; }
-          for (int64_t j = 0; j < nn; ++j) {
-            if (bnd[j]) continue;
-            double mij = M[i * nn + j], aij = A[i * nn + j];
-            if (mij == 0.0 && aij == 0.0) continue;
-            for (int b = 0; b < nt; ++b)
-              at(row, vidx(n, b, comp, j)) += L.td.K[a * nt + b] * mij + (a == b ? ca * aij : 0.0);
-            if (n > 0) at(row, vidx(n - 1, nt - 1, comp, j)) -= L.td.phim1[a] * mij;
-          }
-          for (int64_t p = 0; p < L.Mp; ++p) {
-            double bv = B[(size_t)p * L.Mv + comp * nn + i];
-            if (bv != 0.0) {
-              at(row, pidx(n, a, p)) -= ca * bv;
-              at(pidx(n, a, p), row) -= ca * bv;
-            }
+  auto vidx = [&](int a, int comp, int64_t node) { return a * L.Mv + comp * nn + node; };
+  auto pidx = [&](int a, int64_t p) { return nt * L.Mv + a * L.Mp + p; };
+  for (int a = 0; a < nt; ++a) {
+    double ca = 0.5 * L.tau * L.td.w[a];
+    for (int comp = 0; comp < d; ++comp)
+      for (int64_t i = 0; i < nn; ++i) {
+        int64_t row = vidx(a, comp, i);
+        if (bnd[i]) { at(row, row) = 1.0; continue; }
+        for (int64_t j = 0; j < nn; ++j) {
+          if (bnd[j]) continue;
+          double mij = M[i * nn + j], aij = A[i * nn + j];
+          if (mij == 0.0 && aij == 0.0) continue;
+          for (int b = 0; b < nt; ++b) at(row, vidx(b, comp, j)) += L.td.K[a * nt + b] * mij + (a == b ? ca * aij : 0.0);
+        }
+        for (int64_t p = 0; p < L.Mp; ++p) {
+          double bv = B[(size_t)p * L.Mv + comp * nn + i];
+          if (bv != 0.0) {
+            at(row, pidx(a, p)) -= ca * bv;
+            at(pidx(a, p), row) -= ca * bv;
           }
         }
-      // bordering: <P_slice, M^p c_1> = 0
-      int s = n * nt + a;
-      for (int64_t c = 0; c < L.ncells; ++c)
-        for (int l = 0; l < C; ++l) {
-          at(pidx(n, a, c * C + l), nd + s) = L.mom[(size_t)c * C + l];
-          at(nd + s, pidx(n, a, c * C + l)) = L.mom[(size_t)c * C + l];
-        }
-    }
+      }
+    // bordering: <P_slice, M^p c_1> = 0
+    for (int64_t c = 0; c < L.ncells; ++c)
+      for (int l = 0; l < C; ++l) {
+        at(pidx(a, c * C + l), nd + a) = L.mom[(size_t)c * C + l];
+        at(nd + a, pidx(a, c * C + l)) = L.mom[(size_t)c * C + l];
+      }
+  }
   std::vector<double> Si((size_t)nb * nb);
   if (!invert((int)nb, S.data(), Si.data())) throw Error(-5, "coarse bordered matrix is singular");
-  inv.resize((size_t)nd * nd);
+  Dinv.resize((size_t)nd * nd);
   for (int64_t r = 0; r < nd; ++r)
-    for (int64_t c = 0; c < nd; ++c) inv[(size_t)r * nd + c] = Si[(size_t)c * nb + r];
+    for (int64_t c = 0; c < nd; ++c) Dinv[(size_t)r * nd + c] = Si[(size_t)c * nb + r];
+  // coupling to the previous subinterval (Eq. (DefDtauh), C^n = -C^tau (x) [M_h; 0]):
+  // block entry (a, comp, i) <- (k, comp, j) is -phi_a(-1) M_ij on free pairs;
+  // G = Dinv * block restricted to the columns (k, comp, j)
+  G.assign((size_t)nd * L.Mv, 0.0);
+  std::vector<double> col(nd);
+  for (int comp = 0; comp < d; ++comp)
+    for (int64_t j = 0; j < nn; ++j) {
+      if (bnd[j]) continue;
+      std::fill(col.begin(), col.end(), 0.0);
+      for (int a = 0; a < nt; ++a)
+        for (int64_t i = 0; i < nn; ++i)
+          if (!bnd[i] && M[i * nn + j] != 0.0) col[vidx(a, comp, i)] = -L.td.phim1[a] * M[i * nn + j];
+      for (int64_t r = 0; r < nd; ++r) {
+        double s = 0.0;
+        for (int64_t q = 0; q < nd; ++q)
+          if (col[q] != 0.0) s += Dinv[(size_t)r * nd + q] * col[q];
+        G[(size_t)r * L.Mv + comp * nn + j] = s;
+      }
+    }
 }
 
 // ------------------------------------------------------------ transfers

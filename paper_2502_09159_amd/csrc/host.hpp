@@ -58,8 +58,10 @@ SpaceTables space_tables(int d, int r);
 struct LevelSpec {
   int n, r, k, N;
 };
+// placement 0: Alg. 2 + Alg. 3 (temporal coarsening padded at the fine end);
+// placement 1: r and k halved together on the fine mesh first.
 std::vector<LevelSpec> build_levels(int n, int r, int k, int N, int n_coarse, int r_min, int k_min,
-                                    bool time_h);
+                                    bool time_h, int placement);
 
 struct LevelHost {
   int d = 0, n = 0, r = 0, k = 0, N = 0;
@@ -79,7 +81,7 @@ struct LevelHost {
 };
 
 struct Params {
-  int d, n, n_coarse, r, k, N, r_min, k_min;
+  int d, n, n_coarse, r, k, N, r_min, k_min, placement;
   bool time_h;
   double amp, tau, nu;
   std::function<void(int, const double*, double*)> nu_fn;  // may be empty
@@ -102,8 +104,14 @@ void vanka_factors(const LevelHost& L, VankaFactors& V, int nthreads);
 // Dense local inverse (ncells x b x b, col-major) from the factors.
 void vanka_dense(const LevelHost& L, const VankaFactors& V, std::vector<double>& dense, int nthreads);
 
-// Bordered coarse inverse: the top-left ndofs x ndofs block (row-major).
-void coarse_inverse(const LevelHost& L, std::vector<double>& inv);
+// Coarsest level: the slab matrix is block lower-bidiagonal in time with one
+// diagonal block D per subinterval, so the exact solve is a forward
+// substitution x_n = Dinv b_n - G x_{n-1}.  Dinv: the top-left block of the
+// inverse of D bordered with the per-slice mean-zero pressure constraints
+// (row-major, slab x slab); G = Dinv * (coupling block), restricted to the
+// velocity columns of the previous subinterval's last temporal dof
+// (row-major, slab x Mv).
+void coarse_inverse(const LevelHost& L, std::vector<double>& Dinv, std::vector<double>& G);
 
 // ------------------------------------------------------------ transfer tables
 struct Transfer {

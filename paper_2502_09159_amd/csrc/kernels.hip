@@ -766,23 +766,33 @@ hipError_t launch_restrict(const LevelArgs& F, const LevelArgs& Cs, const Transf
 }
 
 // =====================================================================
-// Coarse solve: x = Cinv b, one wave per row (FP64 arithmetic).
+// Coarse solve: the coarsest slab matrix is block lower-bidiagonal in time,
+// so x_n = Dinv b_n - G x_{n-1,last} (one launch per subinterval, one wave
+// per row, FP64 arithmetic).
 // =====================================================================
 template <typename T>
-__global__ __launch_bounds__(256) void k_coarse(int64_t nd, const double* __restrict__ Ci, const T* __restrict__ b,
-                                                T* __restrict__ x) {
+__global__ __launch_bounds__(256) void k_coarse(int64_t slab, int64_t Mv, int nt, int n,
+                                                const double* __restrict__ Di, const double* __restrict__ G,
+                                                const T* __restrict__ b, T* __restrict__ x) {
   int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   int lane = threadIdx.x % 64;
   double s = 0.0;
-  if (row < nd)
-    for (int64_t j = lane; j < nd; j += 64) s += Ci[row * nd + j] * (double)b[j];
+  if (row < slab) {
+    const T* bn = b + (int64_t)n * slab;
+    for (int64_t j = lane; j < slab; j += 64) s += Di[row * slab + j] * (double)bn[j];
+    if (n > 0) {
+      const T* xp = x + (int64_t)(n - 1) * slab + (int64_t)(nt - 1) * Mv;
+      for (int64_t j = lane; j < Mv; j += 64) s -= G[row * Mv + j] * (double)xp[j];
+    }
+  }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (row < nd && lane == 0) x[row] = (T)s;
+  if (row < slab && lane == 0) x[(int64_t)n * slab + row] = (T)s;
 }
 
 template <typename T>
-hipError_t launch_coarse(int64_t nd, const double* Cinv, const T* b, T* x, hipStream_t s) {
-  k_coarse<T><<<(unsigned)((nd + 3) / 4), 256, 0, s>>>(nd, Cinv, b, x);
+hipError_t launch_coarse(int64_t slab, int64_t Mv, int nt, int N, const double* Dinv, const double* G, const T* b,
+                         T* x, hipStream_t s) {
+  for (int n = 0; n < N; ++n) k_coarse<T><<<(unsigned)((slab + 3) / 4), 256, 0, s>>>(slab, Mv, nt, n, Dinv, G, b, x);
   return hipGetLastError();
 }
 
@@ -937,7 +947,8 @@ hipError_t launch_project_pressure(const LevelArgs& L, const double* mom, double
   template hipError_t launch_restrict<T>(const LevelArgs&, const LevelArgs&, const TransferDev&, const T*,         \
                                          const int*, const int*, const T*, const T*, const T*, T*, T*, T*, T*,      \
                                          hipStream_t);                                                              \
-  template hipError_t launch_coarse<T>(int64_t, const double*, const T*, T*, hipStream_t);                          \
+  template hipError_t launch_coarse<T>(int64_t, int64_t, int, int, const double*, const double*, const T*, T*,  \
+                                        hipStream_t);                          \
   template hipError_t launch_fill<T>(T*, T, int64_t, hipStream_t);                                                  \
   template hipError_t launch_axpy<T>(T*, T, const T*, int64_t, hipStream_t);
 STMG_INST(double)

@@ -45,9 +45,12 @@ hipError_t launch_restrict(const LevelArgs& F, const LevelArgs& Cs, const Transf
                            const int* clo, const int* chi, const T* E, const T* Pt, const T* rf, T* bc, T* tmp1,
                            T* tmp2, T* tmp3, hipStream_t s);
 
-// Coarse solve x = Cinv b (Cinv FP64, nd x nd row-major).
+// Coarse solve by forward substitution over the N subintervals:
+// x_n = Dinv b_n - G x_{n-1}[last temporal dof, velocity] (FP64 matrices,
+// Dinv slab x slab, G slab x Mv, row-major).
 template <typename T>
-hipError_t launch_coarse(int64_t nd, const double* Cinv, const T* b, T* x, hipStream_t s);
+hipError_t launch_coarse(int64_t slab, int64_t Mv, int nt, int N, const double* Dinv, const double* G, const T* b,
+                         T* x, hipStream_t s);
 
 // Vector helpers.
 template <typename T>

@@ -143,7 +143,7 @@ struct stmg_ctx {
   Hier<double> H64;
   Hier<float> H32;
   bool mixed = false;
-  double* Cinv = nullptr;
+  double *Cinv = nullptr, *Cg = nullptr;  // coarsest level: bordered subinterval inverse, coupling
   int64_t nd_coarse = 0;
   double* mom0 = nullptr;  // finest-level pressure moments
   double volume0 = 1.0;
@@ -288,7 +288,7 @@ void vcycle(stmg_ctx* c, Hier<T>& H, int l) {
   DevLevel<T>& D = H.L[l];
   const int last = (int)H.L.size() - 1;
   if (l == last) {
-    HIPCHK(launch_coarse<T>(c->nd_coarse, c->Cinv, D.b, D.x, c->stream));
+    HIPCHK(launch_coarse<T>(D.a.slab, D.a.Mv, D.a.nt, D.a.N, c->Cinv, c->Cg, D.b, D.x, c->stream));
     return;
   }
   HIPCHK(launch_fill<T>(D.x, T(0), D.ndofs, c->stream));
@@ -369,7 +369,7 @@ stmg_status stmg_default_params(stmg_params* p) {
   std::memset(p, 0, sizeof(*p));
   p->dim = 3; p->n_cells_1d = 4; p->n_coarse_1d = 2; p->deform_amp = 0.0;
   p->r = 1; p->k = 1; p->n_sub = 2; p->tau = 0.05; p->nu = 1.0;
-  p->r_min = 1; p->k_min = 1; p->time_h_coarsening = 1; p->nu_pre = 1; p->nu_post = 1; p->omega = 0.8;
+  p->r_min = 1; p->k_min = 1; p->time_h_coarsening = 0; p->placement = 0; p->nu_pre = 1; p->nu_post = 1; p->omega = 0.8;
   p->precision = STMG_FP64; p->vanka_mode = STMG_VANKA_FACTORED; p->device = 0; p->stream = nullptr;
   return STMG_OK;
 }
@@ -387,6 +387,7 @@ static int check_params(const stmg_params* p, std::string& msg) {
   if (!(p->omega > 0) || p->nu_pre < 0 || p->nu_post < 0) { msg = "bad smoother parameters"; return STMG_EINVAL; }
   if (p->precision != STMG_FP64 && p->precision != STMG_MIXED_FP32) { msg = "bad precision"; return STMG_EINVAL; }
   if (p->vanka_mode != STMG_VANKA_FACTORED && p->vanka_mode != STMG_VANKA_DENSE) { msg = "bad vanka_mode"; return STMG_EINVAL; }
+  if (p->placement != 0 && p->placement != 1) { msg = "bad placement"; return STMG_EINVAL; }
   return STMG_OK;
 }
 
@@ -396,7 +397,7 @@ stmg_status stmg_hierarchy(const stmg_params* p, int max_levels, int* levels_out
   if (e) return (stmg_status)e;
   if (!levels_out || !n_levels) return STMG_EINVAL;
   auto L = build_levels(p->n_cells_1d, p->r, p->k, p->n_sub, p->n_coarse_1d, p->r_min, p->k_min,
-                        p->time_h_coarsening != 0);
+                        p->time_h_coarsening != 0, p->placement);
   *n_levels = (int)L.size();
   for (int i = 0; i < (int)L.size() && i < max_levels; ++i) {
     levels_out[4 * i + 0] = L[i].n; levels_out[4 * i + 1] = L[i].r;
@@ -419,14 +420,14 @@ stmg_status stmg_setup(const stmg_params* p, stmg_ctx** out) {
     c->stream = static_cast<hipStream_t>(p->stream);
     Params P;
     P.d = p->dim; P.n = p->n_cells_1d; P.n_coarse = p->n_coarse_1d; P.r = p->r; P.k = p->k; P.N = p->n_sub;
-    P.r_min = p->r_min; P.k_min = p->k_min; P.time_h = p->time_h_coarsening != 0;
+    P.r_min = p->r_min; P.k_min = p->k_min; P.time_h = p->time_h_coarsening != 0; P.placement = p->placement;
     P.amp = p->deform_amp; P.tau = p->tau; P.nu = p->nu;
     if (p->nu_fn) {
       stmg_nu_fn fn = p->nu_fn;
       void* user = p->nu_user;
       P.nu_fn = [fn, user](int n, const double* xyz, double* o) { fn(n, xyz, o, user); };
     }
-    auto specs = build_levels(P.n, P.r, P.k, P.N, P.n_coarse, P.r_min, P.k_min, P.time_h);
+    auto specs = build_levels(P.n, P.r, P.k, P.N, P.n_coarse, P.r_min, P.k_min, P.time_h, P.placement);
     int nthreads = 1;
 #ifdef _OPENMP
     nthreads = omp_get_max_threads();
@@ -439,9 +440,10 @@ stmg_status stmg_setup(const stmg_params* p, stmg_ctx** out) {
       vanka_factors(c->host[l], VF[l], nthreads);
       if (p->vanka_mode == STMG_VANKA_DENSE) vanka_dense(c->host[l], VF[l], dense[l], nthreads);
     }
-    std::vector<double> cinv;
-    coarse_inverse(c->host.back(), cinv);
+    std::vector<double> cinv, cg;
+    coarse_inverse(c->host.back(), cinv, cg);
     c->nd_coarse = c->host.back().ndofs;
+    c->Cg = c->pool.upload<double>(cg, c->stream);
     for (auto& L : c->host) c->verts.push_back(c->pool.upload<double>(L.verts, c->stream));
     c->Cinv = c->pool.upload<double>(cinv, c->stream);
     c->mom0 = c->pool.upload<double>(c->host[0].mom, c->stream);
@@ -610,7 +612,8 @@ stmg_status stmg_prolongate(stmg_ctx* c, int level, const double* coarse, double
 stmg_status stmg_coarse_solve(stmg_ctx* c, const double* b, double* x) {
   if (!c || !b || !x) return STMG_EINVAL;
   return (stmg_status)guarded(c, [&] {
-    HIPCHK(launch_coarse<double>(c->nd_coarse, c->Cinv, b, x, c->stream));
+    const LevelArgs& a = c->H64.L.back().a;
+    HIPCHK(launch_coarse<double>(a.slab, a.Mv, a.nt, a.N, c->Cinv, c->Cg, b, x, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
   });
 }

@@ -30,7 +30,8 @@ class Params(ctypes.Structure):
                 ("deform_amp", ctypes.c_double), ("r", ctypes.c_int), ("k", ctypes.c_int),
                 ("n_sub", ctypes.c_int), ("tau", ctypes.c_double), ("nu", ctypes.c_double),
                 ("nu_fn", NU_FN), ("nu_user", ctypes.c_void_p), ("r_min", ctypes.c_int),
-                ("k_min", ctypes.c_int), ("time_h_coarsening", ctypes.c_int), ("nu_pre", ctypes.c_int),
+                ("k_min", ctypes.c_int), ("time_h_coarsening", ctypes.c_int), ("placement", ctypes.c_int),
+                ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("omega", ctypes.c_double), ("precision", ctypes.c_int),
                 ("vanka_mode", ctypes.c_int), ("device", ctypes.c_int), ("stream", ctypes.c_void_p)]
 

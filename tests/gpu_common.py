@@ -17,6 +17,12 @@ CONFIGS = {
     "r1k1_n8": dict(dim=3, n_cells_1d=8, n_coarse_1d=2, r=1, k=1, n_sub=4, deform_amp=0.03, k_min=1),
     # the C3/C5 element (Q3/P2 x DG(1)) on 4^3, 4 subintervals, variable viscosity
     "c5_small": dict(dim=3, n_cells_1d=4, n_coarse_1d=2, r=2, k=1, n_sub=4, deform_amp=0.03, k_min=1, nu_seed=5),
+    # the same with temporal h-coarsening at the coarse end (N 4 -> 2 -> 1)
+    "r1k1_n8_th": dict(dim=3, n_cells_1d=8, n_coarse_1d=2, r=1, k=1, n_sub=4, deform_amp=0.03, k_min=1,
+                       time_h_coarsening=1),
+    # the C2 element with r and k halved together on the fine mesh (k -> 0)
+    "c2_small_top": dict(dim=3, n_cells_1d=4, n_coarse_1d=2, r=2, k=2, n_sub=2, deform_amp=0.03, k_min=0,
+                         placement=1),
     # 2D Q3/P2 x DG(2) on 8x8
     "2d_r2k2": dict(dim=2, n_cells_1d=8, n_coarse_1d=1, r=2, k=2, n_sub=2, deform_amp=0.03, k_min=1),
 }
@@ -48,7 +54,8 @@ def oracle_mg(name):
     nf = nu_field(cfg)
     return Multigrid(cfg["dim"], cfg["n_cells_1d"], cfg["r"], cfg["k"], cfg["n_sub"], TAU,
                      nu=nf if nf is not None else 1.0, amp=cfg["deform_amp"], n_coarse=cfg["n_coarse_1d"],
-                     k_min=cfg["k_min"], omega=OMEGA)
+                     k_min=cfg["k_min"], omega=OMEGA, time_h=cfg.get("time_h_coarsening", 0) == 1,
+                     placement="top" if cfg.get("placement", 0) == 1 else "paper")
 
 
 def rhs(cfg, seed):

@@ -40,13 +40,20 @@ def test_hierarchy_matches_oracle_rule():
     from oracle.hierarchy import build_levels
     from paper_2502_09159_amd import stmg
     cases = [dict(dim=2, n_cells_1d=4, n_coarse_1d=1, r=1, k=1, n_sub=2),
+             dict(dim=2, n_cells_1d=4, n_coarse_1d=1, r=1, k=1, n_sub=2, time_h_coarsening=1),
+             dict(dim=3, n_cells_1d=16, n_coarse_1d=2, r=2, k=2, n_sub=4, k_min=0, time_h_coarsening=1),
              dict(dim=3, n_cells_1d=16, n_coarse_1d=2, r=2, k=2, n_sub=4, k_min=0),
              dict(dim=3, n_cells_1d=32, n_coarse_1d=2, r=2, k=1, n_sub=8),
-             dict(dim=3, n_cells_1d=8, n_coarse_1d=1, r=2, k=2, n_sub=8, time_h_coarsening=0)]
+             dict(dim=3, n_cells_1d=8, n_coarse_1d=1, r=2, k=2, n_sub=8, time_h_coarsening=0),
+             dict(dim=3, n_cells_1d=16, n_coarse_1d=2, r=2, k=2, n_sub=4, k_min=0, placement=1),
+             dict(dim=3, n_cells_1d=16, n_coarse_1d=2, r=2, k=2, n_sub=4, k_min=0, placement=1,
+                  time_h_coarsening=1),
+             dict(dim=3, n_cells_1d=32, n_coarse_1d=2, r=2, k=1, n_sub=8, time_h_coarsening=1)]
     for c in cases:
         got = stmg.hierarchy(**c)
         ref = build_levels(c["n_cells_1d"], c["r"], c["k"], c["n_sub"], c["n_coarse_1d"], c.get("r_min", 1),
-                           c.get("k_min", 1), c.get("time_h_coarsening", 1) == 1)
+                           c.get("k_min", 1), c.get("time_h_coarsening", 0) == 1,
+                           "top" if c.get("placement", 0) == 1 else "paper")
         assert got == [(l["n"], l["r"], l["k"], l["N"]) for l in ref]
 
 

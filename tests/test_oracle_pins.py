@@ -196,11 +196,19 @@ def test_lid_driven_dof_counts():
 
 
 def test_config_level_lists():
-    """Default placement (reading G12) on the benchmark configurations."""
-    assert [tuple(l.values()) for l in build_levels(4, 1, 1, 2, 1)] == [(4, 1, 1, 2), (2, 1, 1, 2), (1, 1, 1, 1)]
-    c2 = build_levels(16, 2, 2, 4, 2, 1, 0)
-    assert [tuple(l.values()) for l in c2] == [(16, 2, 2, 4), (16, 1, 1, 4), (16, 1, 0, 4), (8, 1, 0, 4),
-                                               (4, 1, 0, 2), (2, 1, 0, 1)]
+    """Level placement on the benchmark configurations: Alg. 2 + Alg. 3
+    (temporal coarsening padded at the fine end, App. C) and the alternative
+    that halves r and k together first (reading G12)."""
+    def rows(levels):
+        return [tuple(l.values()) for l in levels]
+    assert rows(build_levels(4, 1, 1, 2, 1)) == [(4, 1, 1, 2), (2, 1, 1, 2), (1, 1, 1, 2)]
+    assert rows(build_levels(4, 1, 1, 2, 1, time_h=True)) == [(4, 1, 1, 2), (2, 1, 1, 2), (1, 1, 1, 1)]
+    assert rows(build_levels(16, 2, 2, 4, 2, 1, 0)) == [(16, 2, 2, 4), (16, 1, 2, 4), (8, 1, 2, 4), (4, 1, 1, 4),
+                                                        (2, 1, 0, 4)]
+    assert rows(build_levels(16, 2, 2, 4, 2, 1, 2)) == [(16, 2, 2, 4), (16, 1, 2, 4), (8, 1, 2, 4), (4, 1, 2, 4),
+                                                        (2, 1, 2, 4)]
+    c2 = build_levels(16, 2, 2, 4, 2, 1, 0, time_h=True, placement="top")
+    assert rows(c2) == [(16, 2, 2, 4), (16, 1, 1, 4), (16, 1, 0, 4), (8, 1, 0, 4), (4, 1, 0, 2), (2, 1, 0, 1)]
     assert space_time_dofs(2, 4, 1, 1, 2) == 840
     assert space_time_dofs(3, 16, 2, 2, 4) == 4726884
     assert space_time_dofs(3, 32, 2, 1, 4) == 24525592
