@@ -148,7 +148,7 @@ def main():
     achieved = nbytes / (lib_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_vanka_fact (finest level, all 8 colours)", "ms_per_launch_group": round(lib_ms, 4),
+                "kernel": "k_vanka_mfma + k_vanka_gather (finest level)", "ms_per_launch_group": round(lib_ms, 4),
                 "ms_event_bracket": round(ev_ms, 4), "algorithmic_bytes": nbytes}
     op_ms = S.kernel_time(1, level=0, reps=reps)
 

@@ -80,7 +80,8 @@ __device__ __forceinline__ T contract(const T* buf, int p, int dir, const T* M, 
 template <typename T, int D, int Q>
 __global__ __launch_bounds__(64) void k_apply(LevelArgs L, const double* __restrict__ verts,
                                               const T* __restrict__ nu_q, T nu_const, const T* __restrict__ tab,
-                                              const T* __restrict__ x, T* __restrict__ y, int color, T sgn) {
+                                              const T* __restrict__ x, const T* __restrict__ b,
+                                              T* __restrict__ y, T* __restrict__ E, int mode) {
   constexpr int NL = D == 2 ? Q * Q : Q * Q * Q;
   constexpr int CPB = 64 / NL;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -102,9 +103,10 @@ __global__ __launch_bounds__(64) void k_apply(LevelArgs L, const double* __restr
   const int tid = threadIdx.x;
   int slot = tid / NL;
   const int p = tid % NL;
-  const int64_t total = color_count(L.n, D, color);
+  const int64_t total = L.Mp / L.C;
   const int64_t w = (int64_t)blockIdx.x * CPB + slot;
   bool active = slot < CPB && w < total;
+  const T sgn = mode ? T(-1) : T(1);
   if (slot > CPB) slot = CPB;
   T* bufA = cbase + slot * per_cell;
   T* bufB = bufA + NL;
@@ -114,9 +116,8 @@ __global__ __launch_bounds__(64) void k_apply(LevelArgs L, const double* __restr
   T* pv = g2 + NL;
   const int n = blockIdx.y;
 
-  int cc[3];
-  color_cell(L.n, D, color, active ? w : 0, cc);
-  int64_t cell = cc[0] + (int64_t)L.n * (cc[1] + (int64_t)L.n * cc[2]);
+  const int64_t cell = active ? w : 0;
+  int cc[3] = {(int)(cell % L.n), (int)((cell / L.n) % L.n), D == 3 ? (int)(cell / ((int64_t)L.n * L.n)) : 0};
   bool fr;
   int val;
   const int64_t g = gnode<D>(L, cc, p, fr, val);
@@ -271,10 +272,8 @@ __global__ __launch_bounds__(64) void k_apply(LevelArgs L, const double* __restr
         Z = contract<T, Q>(buf, p, dir, sS, true);
         cur ^= 1;
       }
-      if (active && fr) {
-        int64_t id = vidx(L, n, a, comp, g);
-        y[id] += sgn * Z;
-      }
+      if (active)
+        E[cell * (int64_t)D * nt * NL * L.N + ((int64_t)(n * nt + a) * D + comp) * NL + p] = Z;
     }
     // continuity: y_p[l] += -c_a sum_q psi_l div JxW
     g0[p] = -ca * div * jxw;
@@ -282,88 +281,140 @@ __global__ __launch_bounds__(64) void k_apply(LevelArgs L, const double* __restr
     if (active && p < C) {
       T s = 0;
       for (int q = 0; q < NL; ++q) s += spsi[q * C + p] * g0[q];
-      y[pidx(L, n, a, cell, p)] += sgn * s;
+      const int64_t id = pidx(L, n, a, cell, p);
+      y[id] = (mode ? b[id] : T(0)) + sgn * s;
     }
   }
 }
 
-// y = 0 / x on Dirichlet (mode 0), or y = b / b - x on Dirichlet (mode 1)
-template <typename T>
-__global__ void k_apply_init(LevelArgs L, const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y,
-                             int mode, int64_t ndofs) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ndofs) return;
-  int64_t off = i % L.slab;
-  T v = mode ? b[i] : T(0);
-  if (off < (int64_t)L.nt * L.Mv) {
-    int64_t gidx = off % L.nodes;
-    bool bnd = false;
-    for (int j = 0; j < L.d; ++j) {
-      int64_t gj = gidx % L.nn;
-      gidx /= L.nn;
-      if (gj == 0 || gj == L.nn - 1) bnd = true;
+// Velocity rows of y = S x (mode 0) / y = b - S x (mode 1): sum the cell
+// contributions of every node in a fixed order; Dirichlet rows are the identity.
+template <typename T, int D>
+__global__ void k_apply_gather(LevelArgs L, const T* __restrict__ E, const T* __restrict__ x,
+                               const T* __restrict__ b, T* __restrict__ y, int mode) {
+  const int64_t per = (int64_t)L.nt * D * L.nodes;
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)L.N * per) return;
+  const int n = (int)(idx / per);
+  int64_t rem = idx % per;
+  const int a = (int)(rem / ((int64_t)D * L.nodes));
+  rem %= (int64_t)D * L.nodes;
+  const int comp = (int)(rem / L.nodes);
+  const int64_t g = rem % L.nodes;
+  const int64_t id = vidx(L, n, a, comp, g);
+  int gj[3] = {(int)(g % L.nn), (int)((g / L.nn) % L.nn), D == 3 ? (int)(g / ((int64_t)L.nn * L.nn)) : 0};
+  int cj[3][2], ij[3][2], nj[3] = {1, 1, 1};
+  bool bnd = false;
+  for (int j = 0; j < D; ++j) {
+    if (gj[j] == 0 || gj[j] == L.nn - 1) bnd = true;
+    int c = gj[j] / L.q, i = gj[j] % L.q;
+    if (c == L.n) { c = L.n - 1; i = L.q; }
+    if (i == 0 && c > 0) {
+      cj[j][0] = c - 1; ij[j][0] = L.q;
+      cj[j][1] = c;     ij[j][1] = 0;
+      nj[j] = 2;
+    } else {
+      cj[j][0] = c; ij[j][0] = i;
     }
-    if (bnd) v = mode ? b[i] - x[i] : x[i];
   }
-  y[i] = v;
+  if (bnd) {
+    y[id] = mode ? b[id] - x[id] : x[id];
+    return;
+  }
+  const int64_t stride = (int64_t)D * L.nt * L.nloc * L.N;
+  const int64_t off = ((int64_t)(n * L.nt + a) * D + comp) * L.nloc;
+  T s = 0;
+  for (int u = 0; u < (D == 3 ? nj[2] : 1); ++u)
+    for (int v = 0; v < nj[1]; ++v)
+      for (int w = 0; w < nj[0]; ++w) {
+        int64_t cell = cj[0][w] + (int64_t)L.n * (cj[1][v] + (int64_t)L.n * (D == 3 ? cj[2][u] : 0));
+        int i = ij[0][w] + L.Q * (ij[1][v] + L.Q * (D == 3 ? ij[2][u] : 0));
+        s += E[cell * stride + off + i];
+      }
+  y[id] = mode ? b[id] - s : s;
 }
 
 template <typename T, int D, int Q>
 static hipError_t apply_impl(const LevelArgs& L, const double* verts, const T* nu_q, T nu_const, const T* tab,
-                             const T* x, const T* b, T* y, int mode, hipStream_t s) {
+                             const T* x, const T* b, T* y, int mode, T* E, hipStream_t s) {
   constexpr int NL = D == 2 ? Q * Q : Q * Q * Q;
   constexpr int CPB = 64 / NL;
-  int64_t nd = (int64_t)L.N * L.slab;
-  k_apply_init<T><<<(unsigned)((nd + 255) / 256), 256, 0, s>>>(L, x, b, y, mode, nd);
   const int tabn = table_size(Q, L.nt, NL, L.C);
   size_t shm = sizeof(T) * (((tabn + 1) & ~1) + (CPB + 1) * (5 * NL + L.nt * L.C));
-  for (int color = 0; color < (1 << D); ++color) {
-    int64_t tot = 1;
-    for (int j = 0; j < D; ++j) tot *= (L.n - ((color >> j) & 1) + 1) / 2;
-    if (tot == 0) continue;
-    dim3 grid((unsigned)((tot + CPB - 1) / CPB), (unsigned)L.N);
-    k_apply<T, D, Q><<<grid, 64, shm, s>>>(L, verts, nu_q, nu_const, tab, x, y, color, mode ? T(-1) : T(1));
-  }
+  int64_t ncells = L.Mp / L.C;
+  dim3 grid((unsigned)((ncells + CPB - 1) / CPB), (unsigned)L.N);
+  k_apply<T, D, Q><<<grid, 64, shm, s>>>(L, verts, nu_q, nu_const, tab, x, b, y, E, mode);
+  int64_t nv = (int64_t)L.N * L.nt * D * L.nodes;
+  k_apply_gather<T, D><<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(L, E, x, b, y, mode);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_apply(const LevelArgs& L, const double* verts, const T* nu_q, T nu_const, const T* tab,
-                        const T* x, const T* b, T* y, int mode, hipStream_t s) {
-  if (L.d == 2 && L.Q == 3) return apply_impl<T, 2, 3>(L, verts, nu_q, nu_const, tab, x, b, y, mode, s);
-  if (L.d == 2 && L.Q == 4) return apply_impl<T, 2, 4>(L, verts, nu_q, nu_const, tab, x, b, y, mode, s);
-  if (L.d == 3 && L.Q == 3) return apply_impl<T, 3, 3>(L, verts, nu_q, nu_const, tab, x, b, y, mode, s);
-  if (L.d == 3 && L.Q == 4) return apply_impl<T, 3, 4>(L, verts, nu_q, nu_const, tab, x, b, y, mode, s);
+                        const T* x, const T* b, T* y, int mode, T* E, hipStream_t s) {
+  if (L.d == 2 && L.Q == 3) return apply_impl<T, 2, 3>(L, verts, nu_q, nu_const, tab, x, b, y, mode, E, s);
+  if (L.d == 2 && L.Q == 4) return apply_impl<T, 2, 4>(L, verts, nu_q, nu_const, tab, x, b, y, mode, E, s);
+  if (L.d == 3 && L.Q == 3) return apply_impl<T, 3, 3>(L, verts, nu_q, nu_const, tab, x, b, y, mode, E, s);
+  if (L.d == 3 && L.Q == 4) return apply_impl<T, 3, 4>(L, verts, nu_q, nu_const, tab, x, b, y, mode, E, s);
   return hipErrorInvalidValue;
 }
 
 // =====================================================================
 // Cell Vanka, Schur-factored local inverse (Eq. (vanka0), (vanka)).
-// One work item = one spatial cell of one colour, all N subintervals at
-// once (the local matrix is the same for every subinterval).  Local
-// velocity rows (a, i) per component; pressure rows q = (a, l).
-//   z_c = A_s^{-1} r_c           (one m x m inverse for all d N columns)
-//   y_p = H^{-1} (D z - r_p),    y_c = z_c - F_c y_p
-//   x  += omega / valence * y    (colour-deterministic scatter)
+// One work group per spatial cell, all N subintervals at once (the local
+// matrix is the same for every subinterval).  Local velocity rows (a, i) per
+// component; pressure rows q = (a, l).
+//   Z = A_s^{-1} R               (MFMA: mp x mp times mp x (d N), one pass over A_s^{-1})
+//   y_p = H^{-1} (D Z - r_p),    y_c = z_c - F_c y_p
+//   x_p += omega y_p             (pressure dofs belong to one cell)
+//   E   = y_v                    (velocity: summed per node by k_vanka_gather)
+// MFMA 16x16x4 operand order: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// accumulator element v holds D[row][l%16] with row = 4 (l/16) + v for FP32
+// and row = l/16 + 4 v for FP64 (both checked on gfx950).
 // =====================================================================
+template <typename T>
+struct mfma_vec;
+template <>
+struct mfma_vec<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane / 16) + v; }
+};
+template <>
+struct mfma_vec<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return lane / 16 + 4 * v; }
+};
+
 template <typename T, int D, int N>
-__global__ __launch_bounds__(256) void k_vanka_fact(LevelArgs L, int color, const T* __restrict__ As_inv,
+__global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __restrict__ Asw,
                                                     const T* __restrict__ Bm, const T* __restrict__ F,
                                                     const T* __restrict__ Hinv, const T* __restrict__ coef,
-                                                    const T* __restrict__ r, T* __restrict__ x, T omega) {
+                                                    const T* __restrict__ r, T* __restrict__ x, T omega,
+                                                    T* __restrict__ E) {
   constexpr int DN = D * N;
+  constexpr int NCT = (DN + 15) / 16;  // column tiles of 16
+  constexpr int DNP = NCT * 16;
+  typedef typename mfma_vec<T>::v4 v4;
   const int nl = L.nloc, nt = L.nt, C = L.C, m = nt * nl, P = nt * C;
+  const int mp = (m + 15) & ~15, nkb = mp / 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* R = reinterpret_cast<T*>(smem_raw);
-  T* Z = R + m * DN;
-  T* Rp = Z + m * DN;
+  T* RZ = reinterpret_cast<T*>(smem_raw);  // R (B-operand order), then Z (row-major mp x DNP)
+  T* Rp = RZ + (size_t)mp * DNP;
   T* S = Rp + P * N;
   T* YP = S + P * N;
   T* sc = YP + P * N;
-  int cc[3];
-  color_cell(L.n, D, color, blockIdx.x, cc);
-  const int64_t cell = cc[0] + (int64_t)L.n * (cc[1] + (int64_t)L.n * cc[2]);
+  const int64_t cell = blockIdx.x;
+  int cc[3] = {(int)(cell % L.n), (int)((cell / L.n) % L.n), (int)(cell / ((int64_t)L.n * L.n))};
   const int tid = threadIdx.x;
+  // ---- gather r into B-operand order; padded rows/columns are zero
+  for (int t = tid; t < mp * DNP; t += blockDim.x) RZ[t] = 0;
+  __syncthreads();
   for (int t = tid; t < m * DN; t += blockDim.x) {
     int i = t % nl, rest = t / nl;
     int a = rest % nt;
@@ -372,7 +423,9 @@ __global__ __launch_bounds__(256) void k_vanka_fact(LevelArgs L, int color, cons
     bool fr;
     int val;
     int64_t g = gnode<D>(L, cc, i, fr, val);
-    R[(a * nl + i) * DN + comp * N + n] = fr ? r[vidx(L, n, a, comp, g)] : T(0);
+    int K = a * nl + i, col = comp * N + n;
+    int ct = col / 16, jj = col % 16, kb = K / 16, rem = K % 16;
+    RZ[(((size_t)ct * nkb + kb) * 64 + jj + 16 * (rem / 4)) * 4 + (rem % 4)] = fr ? r[vidx(L, n, a, comp, g)] : T(0);
   }
   for (int t = tid; t < P * N; t += blockDim.x) {
     int q = t % P, n = t / P;
@@ -380,35 +433,52 @@ __global__ __launch_bounds__(256) void k_vanka_fact(LevelArgs L, int color, cons
   }
   if (tid < nt) sc[tid] = coef[tid];
   __syncthreads();
-  const T* A = As_inv + cell * (int64_t)m * m;
-  for (int row = tid; row < m; row += blockDim.x) {
-    T acc[DN];
+  // ---- Z = A_s^{-1} R on the matrix cores
+  const int wave = tid / 64, lane = tid % 64;
+  const int nwave = blockDim.x / 64;
+  const T* A = Asw + (size_t)cell * mp * mp;
+  v4 acc[4][NCT];  // up to 4 row tiles per wave (mp <= 256)
 #pragma unroll
-    for (int c = 0; c < DN; ++c) acc[c] = 0;
-    int j = 0;
-    for (; j + 4 <= m; j += 4) {
-      T a0 = A[(int64_t)j * m + row], a1 = A[(int64_t)(j + 1) * m + row];
-      T a2 = A[(int64_t)(j + 2) * m + row], a3 = A[(int64_t)(j + 3) * m + row];
+  for (int it = 0; it < 4; ++it) {
+    const int t = wave + it * nwave;
+    if (t < nkb) {
 #pragma unroll
-      for (int c = 0; c < DN; ++c)
-        acc[c] += a0 * R[j * DN + c] + a1 * R[(j + 1) * DN + c] + a2 * R[(j + 2) * DN + c] +
-                  a3 * R[(j + 3) * DN + c];
+      for (int ct = 0; ct < NCT; ++ct) acc[it][ct] = v4{0, 0, 0, 0};
+      const T* At = A + (size_t)t * nkb * 256;
+      for (int kb = 0; kb < nkb; ++kb) {
+        const T* ap = At + ((size_t)kb * 64 + lane) * 4;
+        T a0 = ap[0], a1 = ap[1], a2 = ap[2], a3 = ap[3];
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          const T* bp = RZ + (((size_t)ct * nkb + kb) * 64 + lane) * 4;
+          acc[it][ct] = mfma_vec<T>::mma(a0, bp[0], acc[it][ct]);
+          acc[it][ct] = mfma_vec<T>::mma(a1, bp[1], acc[it][ct]);
+          acc[it][ct] = mfma_vec<T>::mma(a2, bp[2], acc[it][ct]);
+          acc[it][ct] = mfma_vec<T>::mma(a3, bp[3], acc[it][ct]);
+        }
+      }
     }
-    for (; j < m; ++j) {
-      T a0 = A[(int64_t)j * m + row];
+  }
+  __syncthreads();  // every wave is done reading R
 #pragma unroll
-      for (int c = 0; c < DN; ++c) acc[c] += a0 * R[j * DN + c];
-    }
+  for (int it = 0; it < 4; ++it) {
+    const int t = wave + it * nwave;
+    if (t < nkb)
 #pragma unroll
-    for (int c = 0; c < DN; ++c) Z[row * DN + c] = acc[c];
+      for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          RZ[(size_t)(t * 16 + mfma_vec<T>::row(lane, v)) * DNP + ct * 16 + lane % 16] = acc[it][ct][v];
   }
   __syncthreads();
+  T* Z = RZ;
+  // ---- pressure Schur complement
   const T* B = Bm + cell * (int64_t)C * D * nl;
   for (int t = tid; t < P * N; t += blockDim.x) {
     int q = t / N, n = t % N, a = q / C, l = q % C;
     T s = 0;
     for (int comp = 0; comp < D; ++comp)
-      for (int i = 0; i < nl; ++i) s += B[(l * D + comp) * nl + i] * Z[(a * nl + i) * DN + comp * N + n];
+      for (int i = 0; i < nl; ++i) s += B[(l * D + comp) * nl + i] * Z[(size_t)(a * nl + i) * DNP + comp * N + n];
     S[q * N + n] = -sc[a] * s - Rp[q * N + n];
   }
   __syncthreads();
@@ -418,52 +488,91 @@ __global__ __launch_bounds__(256) void k_vanka_fact(LevelArgs L, int color, cons
     T s = 0;
     for (int q = 0; q < P; ++q) s += H[q * P + pp] * S[q * N + n];
     YP[pp * N + n] = s;
-    int64_t id = pidx(L, n, pp / C, cell, pp % C);
-    x[id] += omega * s;
+    x[pidx(L, n, pp / C, cell, pp % C)] += omega * s;
   }
   __syncthreads();
+  // ---- velocity: y = z - F y_p into the cell-local buffer, layout
+  // E[cell][(n nt + a) D + comp][i]
   const T* Fc = F + cell * (int64_t)D * m * P;
+  T* Ec = E + cell * (int64_t)D * m * N;
   for (int row2 = tid; row2 < D * m; row2 += blockDim.x) {
     int comp = row2 / m, row = row2 % m, a = row / nl, i = row % nl;
-    T acc[N];
+    T acc2[N];
 #pragma unroll
-    for (int n = 0; n < N; ++n) acc[n] = Z[row * DN + comp * N + n];
+    for (int n = 0; n < N; ++n) acc2[n] = Z[(size_t)row * DNP + comp * N + n];
     for (int q = 0; q < P; ++q) {
       T f = Fc[((int64_t)comp * P + q) * m + row];
 #pragma unroll
-      for (int n = 0; n < N; ++n) acc[n] -= f * YP[q * N + n];
+      for (int n = 0; n < N; ++n) acc2[n] -= f * YP[q * N + n];
     }
-    bool fr;
-    int val;
-    int64_t g = gnode<D>(L, cc, i, fr, val);
-    if (fr) {
-      T wgt = omega / T(val);
 #pragma unroll
-      for (int n = 0; n < N; ++n) x[vidx(L, n, a, comp, g)] += wgt * acc[n];
-    }
+    for (int n = 0; n < N; ++n) Ec[((int64_t)(n * nt + a) * D + comp) * nl + i] = acc2[n];
   }
 }
 
-template <typename T, int D, int N>
-static hipError_t vanka_fact_impl(const LevelArgs& L, const T* As_inv, const T* Bm, const T* F, const T* Hinv,
-                                  const T* coef, const T* r, T* x, T omega, hipStream_t s) {
-  const int m = L.nt * L.nloc, P = L.nt * L.C;
-  size_t shm = sizeof(T) * (2 * (size_t)m * D * N + 3 * (size_t)P * N + L.nt + 2);
-  if (shm > 160 * 1024) return hipErrorInvalidValue;
-  for (int color = 0; color < (1 << D); ++color) {
-    int64_t tot = 1;
-    for (int j = 0; j < D; ++j) tot *= (L.n - ((color >> j) & 1) + 1) / 2;
-    if (tot == 0) continue;
-    k_vanka_fact<T, D, N><<<(unsigned)tot, 256, shm, s>>>(L, color, As_inv, Bm, F, Hinv, coef, r, x, omega);
+// x_v += omega / valence * (sum over the cells containing the node of E),
+// cells taken in a fixed order (deterministic); Dirichlet nodes unchanged.
+template <typename T, int D>
+__global__ void k_vanka_gather(LevelArgs L, const T* __restrict__ E, T* __restrict__ x, T omega) {
+  const int64_t per = (int64_t)L.nt * D * L.nodes;  // velocity dofs of one subinterval
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)L.N * per) return;
+  const int n = (int)(idx / per);
+  int64_t rem = idx % per;
+  const int a = (int)(rem / ((int64_t)D * L.nodes));
+  rem %= (int64_t)D * L.nodes;
+  const int comp = (int)(rem / L.nodes);
+  const int64_t g = rem % L.nodes;
+  int gj[3] = {(int)(g % L.nn), (int)((g / L.nn) % L.nn), D == 3 ? (int)(g / ((int64_t)L.nn * L.nn)) : 0};
+  // cells containing the node along each direction: (cell, local index)
+  int cj[3][2], ij[3][2], nj[3];
+  for (int j = 0; j < D; ++j) {
+    if (gj[j] == 0 || gj[j] == L.nn - 1) return;  // Dirichlet
+    int c = gj[j] / L.q, i = gj[j] % L.q;
+    if (i == 0) {
+      cj[j][0] = c - 1; ij[j][0] = L.q;
+      cj[j][1] = c;     ij[j][1] = 0;
+      nj[j] = 2;
+    } else {
+      cj[j][0] = c; ij[j][0] = i;
+      nj[j] = 1;
+    }
   }
+  const int64_t stride = (int64_t)D * L.nt * L.nloc * L.N;  // per cell
+  const int64_t off = ((int64_t)(n * L.nt + a) * D + comp) * L.nloc;
+  T s = 0;
+  int val = 1;
+  for (int j = 0; j < D; ++j) val *= nj[j];
+  for (int u = 0; u < (D == 3 ? nj[2] : 1); ++u)
+    for (int v = 0; v < nj[1]; ++v)
+      for (int w = 0; w < nj[0]; ++w) {
+        int64_t cell = cj[0][w] + (int64_t)L.n * (cj[1][v] + (int64_t)L.n * (D == 3 ? cj[2][u] : 0));
+        int i = ij[0][w] + L.Q * (ij[1][v] + L.Q * (D == 3 ? ij[2][u] : 0));
+        s += E[cell * stride + off + i];
+      }
+  x[vidx(L, n, a, comp, g)] += omega / T(val) * s;
+}
+
+template <typename T, int D, int N>
+static hipError_t vanka_fact_impl(const LevelArgs& L, const T* Asw, const T* Bm, const T* F, const T* Hinv,
+                                  const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s) {
+  const int m = L.nt * L.nloc, P = L.nt * L.C, mp = (m + 15) & ~15;
+  constexpr int DNP = ((D * N + 15) / 16) * 16;
+  if (mp / 16 > 16) return hipErrorInvalidValue;  // at most 4 row tiles per wave
+  size_t shm = sizeof(T) * ((size_t)mp * DNP + 3 * (size_t)P * N + L.nt + 2);
+  if (shm > 160 * 1024) return hipErrorInvalidValue;
+  int64_t ncells = L.Mp / L.C;
+  k_vanka_mfma<T, D, N><<<(unsigned)ncells, 256, shm, s>>>(L, Asw, Bm, F, Hinv, coef, r, x, omega, E);
+  int64_t nv = (int64_t)L.N * L.nt * D * L.nodes;
+  k_vanka_gather<T, D><<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(L, E, x, omega);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_vanka_factored(const LevelArgs& L, const T* As_inv, const T* Bm, const T* F, const T* Hinv,
-                                 const T* coef, const T* r, T* x, T omega, hipStream_t s) {
+hipError_t launch_vanka_factored(const LevelArgs& L, const T* Asw, const T* Bm, const T* F, const T* Hinv,
+                                 const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s) {
 #define STMG_VF(DD, NN) \
-  if (L.d == DD && L.N == NN) return vanka_fact_impl<T, DD, NN>(L, As_inv, Bm, F, Hinv, coef, r, x, omega, s);
+  if (L.d == DD && L.N == NN) return vanka_fact_impl<T, DD, NN>(L, Asw, Bm, F, Hinv, coef, r, x, omega, E, s);
   STMG_VF(2, 1) STMG_VF(2, 2) STMG_VF(2, 4) STMG_VF(2, 8)
   STMG_VF(3, 1) STMG_VF(3, 2) STMG_VF(3, 4) STMG_VF(3, 8)
 #undef STMG_VF
@@ -937,9 +1046,9 @@ hipError_t launch_project_pressure(const LevelArgs& L, const double* mom, double
 // explicit instantiations
 #define STMG_INST(T)                                                                                                \
   template hipError_t launch_apply<T>(const LevelArgs&, const double*, const T*, T, const T*, const T*, const T*,  \
-                                      T*, int, hipStream_t);                                                        \
+                                      T*, int, T*, hipStream_t);                                                    \
   template hipError_t launch_vanka_factored<T>(const LevelArgs&, const T*, const T*, const T*, const T*, const T*, \
-                                               const T*, T*, T, hipStream_t);                                       \
+                                               const T*, T*, T, T*, hipStream_t);                                   \
   template hipError_t launch_vanka_dense<T>(const LevelArgs&, const T*, const T*, T*, T, hipStream_t);             \
   template hipError_t launch_prolongate_add<T>(const LevelArgs&, const LevelArgs&, const TransferDev&, const T*,   \
                                                const int*, const int*, const T*, const T*, const T*, T*, T*, T*,    \

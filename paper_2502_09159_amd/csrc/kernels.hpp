@@ -17,15 +17,26 @@ struct LevelArgs {
 // [S (QxQ) | Dg (QxQ) | gx (Q) | gw (Q) | K (nt x nt) | phim1 (nt) | coef (nt) | psi (nloc x C)].
 inline int table_size(int Q, int nt, int nloc, int C) { return 2 * Q * Q + 2 * Q + nt * nt + 2 * nt + nloc * C; }
 
-// Operator: y = S x (mode 0) or y = b - S x (mode 1), colored, deterministic.
+// Operator: y = S x (mode 0) or y = b - S x (mode 1).  Cell contributions to
+// velocity nodes go to the cell-local scratch E (ncells * d * m * N values)
+// and are summed per node in a fixed order (deterministic, no atomics).
 template <typename T>
 hipError_t launch_apply(const LevelArgs& L, const double* verts, const T* nu_q, T nu_const, const T* tab,
-                        const T* x, const T* b, T* y, int mode, hipStream_t s);
+                        const T* x, const T* b, T* y, int mode, T* E, hipStream_t s);
 
 // Vanka correction with factored local inverses: x += omega D^-1 sum R^T A^-1 R r.
+// Asw: A_s^{-1} of every cell in MFMA operand order (see vanka_swizzle_index),
+// padded to mp = 16 ceil(m/16); E: cell-local scratch of ncells * d * m * N
+// values (the velocity corrections, summed per node by a gather kernel).
 template <typename T>
-hipError_t launch_vanka_factored(const LevelArgs& L, const T* As_inv, const T* Bm, const T* F, const T* Hinv,
-                                 const T* coef, const T* r, T* x, T omega, hipStream_t s);
+hipError_t launch_vanka_factored(const LevelArgs& L, const T* Asw, const T* Bm, const T* F, const T* Hinv,
+                                 const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s);
+// Position of A_s^{-1}[row][k] inside one cell's swizzled block (mp x mp):
+// row tile t = row/16, k chunk kb = k/16, lane = row%16 + 16*((k%16)/4), slot k%4.
+inline int64_t vanka_swizzle_index(int mp, int row, int k) {
+  int t = row / 16, kb = k / 16, lane = row % 16 + 16 * ((k % 16) / 4), sl = k % 4;
+  return (((int64_t)t * (mp / 16) + kb) * 64 + lane) * 4 + sl;
+}
 // Same with one dense local inverse per cell.
 template <typename T>
 hipError_t launch_vanka_dense(const LevelArgs& L, const T* Ainv, const T* r, T* x, T omega, hipStream_t s);

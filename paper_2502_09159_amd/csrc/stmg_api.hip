@@ -76,7 +76,8 @@ struct DevLevel {
   T* nu_q = nullptr;
   T nu_const = 1;
   T* tab = nullptr;
-  T *As_inv = nullptr, *Bm = nullptr, *F = nullptr, *Hinv = nullptr, *coef = nullptr, *dense = nullptr;
+  T *Asw = nullptr, *Bm = nullptr, *F = nullptr, *Hinv = nullptr, *coef = nullptr, *dense = nullptr;
+  T* E = nullptr;  // cell-local scratch of the Vanka correction
   T *b = nullptr, *x = nullptr, *r = nullptr;
   int64_t ndofs = 0;
 };
@@ -193,6 +194,8 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
     if (!L.nu_q.empty()) D.nu_q = c->pool.upload<T>(L.nu_q, s);
     D.tab = c->pool.upload<T>(pack_tables(L), s);
     D.ndofs = L.ndofs;
+    // cell-local scratch shared by the operator and the smoother of this level
+    D.E = c->pool.alloc<T>((size_t)L.ncells * L.d * L.nt * L.nloc * L.N);
     D.b = c->pool.alloc<T>(L.ndofs);
     D.x = c->pool.alloc<T>(L.ndofs);
     D.r = c->pool.alloc<T>(L.ndofs);
@@ -202,7 +205,15 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
       if (c->p.vanka_mode == STMG_VANKA_DENSE) {
         D.dense = c->pool.upload<T>(dense[l], s);
       } else {
-        D.As_inv = c->pool.upload<T>(V.As_inv, s);
+        // A_s^{-1} in MFMA operand order, padded to a multiple of 16
+        const int m = V.m, mp = (m + 15) & ~15;
+        std::vector<T> sw((size_t)L.ncells * mp * mp, T(0));
+        for (int64_t cl = 0; cl < L.ncells; ++cl)
+          for (int k = 0; k < m; ++k)
+            for (int row = 0; row < m; ++row)
+              sw[(size_t)cl * mp * mp + vanka_swizzle_index(mp, row, k)] =
+                  (T)V.As_inv[((size_t)cl * m + k) * m + row];
+        D.Asw = c->pool.upload<T>(sw, s);
         D.Bm = c->pool.upload<T>(V.Bm, s);
         D.F = c->pool.upload<T>(V.F, s);
         D.Hinv = c->pool.upload<T>(V.Hinv, s);
@@ -242,7 +253,7 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
 // ------------------------------------------------------------- level ops
 template <typename T>
 void op_apply(stmg_ctx* c, DevLevel<T>& D, const T* x, const T* b, T* y, int mode) {
-  HIPCHK(launch_apply<T>(D.a, D.verts, D.nu_q, D.nu_const, D.tab, x, b, y, mode, c->stream));
+  HIPCHK(launch_apply<T>(D.a, D.verts, D.nu_q, D.nu_const, D.tab, x, b, y, mode, D.E, c->stream));
 }
 
 template <typename T>
@@ -251,7 +262,7 @@ void op_vanka(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x) {
   if (c->p.vanka_mode == STMG_VANKA_DENSE)
     HIPCHK(launch_vanka_dense<T>(D.a, D.dense, r, x, om, c->stream));
   else
-    HIPCHK(launch_vanka_factored<T>(D.a, D.As_inv, D.Bm, D.F, D.Hinv, D.coef, r, x, om, c->stream));
+    HIPCHK(launch_vanka_factored<T>(D.a, D.Asw, D.Bm, D.F, D.Hinv, D.coef, r, x, om, D.E, c->stream));
 }
 
 template <typename T>
