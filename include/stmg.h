@@ -182,6 +182,50 @@ stmg_status stmg_solve(stmg_ctx* ctx, const double* b, double* x, double rtol, i
  * vector, finest level). */
 stmg_status stmg_project_pressure_mean_zero(stmg_ctx* ctx, double* x);
 
+/* ------------------------------------------------------------------------
+ * Learned correction (an addition to the paper's method): after every Vanka
+ * sweep on a 3D level with the Q2/P1 x DG(1) element, a 3-layer 3x3x3
+ * convolutional network maps each space-time cell's residual (15 channels:
+ * 6 velocity, 8 pressure broadcast, 1 Dirichlet mask; scaled by its 2-norm
+ * s_T) to a correction (6 velocity channels at the nodes, 8 pressure values
+ * averaged over the nodes; times s_T), summed over cells with the valence
+ * weighting of the Vanka patches.  BF16 operands on the matrix cores, FP32
+ * accumulation.  If a correction raises the residual 2-norm on its level it
+ * is undone and the network is switched off for the rest of the solve.
+ * Weights: STMG_NET_PARAMS FP32 values, W1 (32x15x27), W2 (32x32x27),
+ * W3 (14x32x27), each [c_out][c_in][offset], offset (dx+1)+3(dy+1)+9(dz+1).
+ * ------------------------------------------------------------------------ */
+#define STMG_NET_PARAMS 52704
+
+/* Copy host weights into the context (allocates the network state). */
+stmg_status stmg_learned_load(stmg_ctx* ctx, const float* weights_host, size_t n);
+/* Read the current weights back (e.g. after training). */
+stmg_status stmg_learned_weights(const stmg_ctx* ctx, float* weights_host, size_t n);
+/* Switch the correction on/off inside stmg_vcycle / stmg_solve. */
+stmg_status stmg_learned_enable(stmg_ctx* ctx, int on);
+
+/* Training pairs on the finest level (3D, r=1, k=1): run the first V-cycle
+ * from x = 0 for right-hand side b and record (r, e = xstar - x) after the
+ * presmoothing sweep and after the postsmoothing sweep.  r_out and e_out are
+ * device FP64 arrays of 2 * n_dofs (pair 0, then pair 1). */
+stmg_status stmg_learned_record(stmg_ctx* ctx, const double* b, const double* xstar, double* r_out, double* e_out);
+
+/* Train with Adam (lr, beta = 0.9/0.999) on n_pairs device FP32 pairs
+ * (r_pairs, e_pairs: n_pairs x n_dofs of the finest level) for `epochs`
+ * passes; a batch is `batch` consecutive space-time cells of one pair, the
+ * batch order is a permutation drawn from `seed`.  The loss of every step,
+ * sum |net - e|^2 / sum |e|^2 over the batch, goes to loss_hist (host, at
+ * least epochs * n_pairs * ceil(cells per pair / batch) values). */
+stmg_status stmg_learned_train(stmg_ctx* ctx, const float* r_pairs, const float* e_pairs, int n_pairs,
+                               uint64_t seed, int epochs, int batch, float lr, float* loss_hist);
+
+/* Test hooks on one level (3D, r=1, k=1), FP64 in and out:
+ * u = sum_T R_T^T s_T net(R_T r / s_T) (the correction, no residual check);
+ * grad = d/dW [sum |net - e|^2 / sum |e|^2] over all cells of the level. */
+stmg_status stmg_learned_correction(stmg_ctx* ctx, int level, const double* r, double* u);
+stmg_status stmg_learned_gradient(stmg_ctx* ctx, int level, const double* r, const double* e, float* grad_host,
+                                  double* loss);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libstmg.so")
-SOURCES = ["host.cpp", "kernels.hip", "stmg_api.hip"]
+SOURCES = ["host.cpp", "kernels.hip", "learned.hip", "stmg_api.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "-fopenmp",
     "--offload-arch=gfx950",

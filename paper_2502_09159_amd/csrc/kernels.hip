@@ -569,6 +569,14 @@ static hipError_t vanka_fact_impl(const LevelArgs& L, const T* Asw, const T* Bm,
 }
 
 template <typename T>
+hipError_t launch_vanka_gather_only(const LevelArgs& L, const T* E, T* x, T omega, hipStream_t s) {
+  int64_t nv = (int64_t)L.N * L.nt * L.d * L.nodes;
+  if (L.d == 3) k_vanka_gather<T, 3><<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(L, E, x, omega);
+  else k_vanka_gather<T, 2><<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(L, E, x, omega);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_vanka_factored(const LevelArgs& L, const T* Asw, const T* Bm, const T* F, const T* Hinv,
                                  const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s) {
 #define STMG_VF(DD, NN) \
@@ -1056,6 +1064,7 @@ hipError_t launch_project_pressure(const LevelArgs& L, const double* mom, double
   template hipError_t launch_restrict<T>(const LevelArgs&, const LevelArgs&, const TransferDev&, const T*,         \
                                          const int*, const int*, const T*, const T*, const T*, T*, T*, T*, T*,      \
                                          hipStream_t);                                                              \
+  template hipError_t launch_vanka_gather_only<T>(const LevelArgs&, const T*, T*, T, hipStream_t);                \
   template hipError_t launch_coarse<T>(int64_t, int64_t, int, int, const double*, const double*, const T*, T*,  \
                                         hipStream_t);                          \
   template hipError_t launch_fill<T>(T*, T, int64_t, hipStream_t);                                                  \

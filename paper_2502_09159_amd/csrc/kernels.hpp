@@ -37,6 +37,9 @@ inline int64_t vanka_swizzle_index(int mp, int row, int k) {
   int t = row / 16, kb = k / 16, lane = row % 16 + 16 * ((k % 16) / 4), sl = k % 4;
   return (((int64_t)t * (mp / 16) + kb) * 64 + lane) * 4 + sl;
 }
+// x_v += omega / valence * sum_cells E (the velocity half of a patch update).
+template <typename T>
+hipError_t launch_vanka_gather_only(const LevelArgs& L, const T* E, T* x, T omega, hipStream_t s);
 // Same with one dense local inverse per cell.
 template <typename T>
 hipError_t launch_vanka_dense(const LevelArgs& L, const T* Ainv, const T* r, T* x, T omega, hipStream_t s);

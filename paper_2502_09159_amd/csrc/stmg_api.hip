@@ -18,6 +18,7 @@
 #include "../../include/stmg.h"
 #include "host.hpp"
 #include "kernels.hpp"
+#include "learned.hpp"
 
 using namespace stmg;
 
@@ -154,6 +155,10 @@ struct stmg_ctx {
   std::vector<double> history;
   bool phase_timing = false;
   EventTimer t_smooth, t_vcyc, t_op;
+  // learned correction
+  NetDev net;
+  bool net_ready = false, learned_on = false, learned_disabled = false;
+  std::vector<void*> lsave;  // per level: copy of x before a correction
 };
 
 namespace {
@@ -266,7 +271,10 @@ void op_vanka(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x) {
 }
 
 template <typename T>
-void op_smooth(stmg_ctx* c, DevLevel<T>& D, const T* b, T* x, int steps, bool zero_start) {
+void learned_step(stmg_ctx* c, DevLevel<T>& D, int level, const T* b, T* x);
+
+template <typename T>
+void op_smooth(stmg_ctx* c, DevLevel<T>& D, const T* b, T* x, int steps, bool zero_start, int level = -1) {
   for (int s = 0; s < steps; ++s) {
     const T* r = b;
     if (!(zero_start && s == 0)) {
@@ -276,6 +284,7 @@ void op_smooth(stmg_ctx* c, DevLevel<T>& D, const T* b, T* x, int steps, bool ze
     if (c->phase_timing) c->t_smooth.a(c->stream);
     op_vanka<T>(c, D, r, x);
     if (c->phase_timing) c->t_smooth.b(c->stream);
+    if (level >= 0) learned_step<T>(c, D, level, b, x);
   }
 }
 
@@ -293,6 +302,76 @@ void op_prolongate_add(stmg_ctx* c, Hier<T>& H, int l, const T* coarse, T* fine)
                                   X.tmp2, X.tmp3, c->stream));
 }
 
+// ------------------------------------------------------------- learned
+constexpr int64_t kNetChunk = 65536;  // samples per inference chunk
+
+void net_alloc(stmg_ctx* c, int64_t batch) {
+  NetDev& N = c->net;
+  if (!c->net_ready) {
+    N.w = c->pool.alloc<float>(kNetParams);
+    N.m = c->pool.alloc<float>(kNetParams);
+    N.v = c->pool.alloc<float>(kNetParams);
+    N.g = c->pool.alloc<float>(kNetParams);
+    N.fw = c->pool.alloc<uint16_t>(27 * (16 * 32 + 32 * 32 + 32 * 16));
+    N.bw = c->pool.alloc<uint16_t>(27 * (16 * 32 + 32 * 32));
+    N.cap = kNetChunk;
+    N.x = c->pool.alloc<uint16_t>(N.cap * 512);
+    N.h1 = c->pool.alloc<uint16_t>(N.cap * 1024);
+    N.h2 = c->pool.alloc<uint16_t>(N.cap * 1024);
+    N.y = c->pool.alloc<float>(N.cap * 512);
+    N.dy = c->pool.alloc<uint16_t>(N.cap * 512);
+    N.scale = c->pool.alloc<float>(N.cap);
+    N.mask = c->pool.alloc<float>(N.cap * 27);
+    N.tv = c->pool.alloc<float>(N.cap * 162);
+    N.tp = c->pool.alloc<float>(N.cap * 8);
+    N.red = c->pool.alloc<double>(2 * N.cap + 8);
+    HIPCHK(launch_fill<float>(N.m, 0.0f, kNetParams, c->stream));
+    HIPCHK(launch_fill<float>(N.v, 0.0f, kNetParams, c->stream));
+    c->net_ready = true;
+  }
+  int64_t nb = (std::min<int64_t>(batch, N.cap) + 7) / 8;
+  if (nb > N.pcap) {
+    N.partial = c->pool.alloc<float>((size_t)nb * kNetParams);
+    N.pcap = nb;
+  }
+}
+
+bool net_level(const LevelArgs& a) { return a.d == 3 && a.Q == 3 && a.nt == 2; }
+
+// u (velocity into E then gathered with weight 1, pressure added) += net correction of r
+template <typename T>
+void net_correct(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x) {
+  const int64_t total = (int64_t)D.a.N * (D.a.Mp / D.a.C);
+  for (int64_t first = 0; first < total; first += kNetChunk) {
+    int64_t cnt = std::min<int64_t>(kNetChunk, total - first);
+    HIPCHK(net_inputs<T>(D.a, c->net, r, (const T*)nullptr, first, cnt, c->stream));
+    HIPCHK(net_forward(c->net, cnt, c->stream));
+    HIPCHK(net_correction<T>(D.a, c->net, first, cnt, D.E, x, c->stream));
+  }
+  HIPCHK(launch_vanka_gather_only<T>(D.a, D.E, x, T(1), c->stream));
+}
+
+template <typename T>
+double norm2(stmg_ctx* c, const T* v, int64_t n);
+
+// After a Vanka sweep: r = b - S x, x' = x + net(r); keep x' only if the
+// residual 2-norm on this level does not grow, otherwise undo and switch off.
+template <typename T>
+void learned_step(stmg_ctx* c, DevLevel<T>& D, int level, const T* b, T* x) {
+  if (!c->learned_on || c->learned_disabled || !c->net_ready || !net_level(D.a)) return;
+  op_apply<T>(c, D, x, b, D.r, 1);
+  const double r0 = norm2<T>(c, D.r, D.ndofs);
+  T* save = static_cast<T*>(c->lsave[level]);
+  HIPCHK(hipMemcpyAsync(save, x, D.ndofs * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+  net_correct<T>(c, D, D.r, x);
+  op_apply<T>(c, D, x, b, D.r, 1);
+  const double r1 = norm2<T>(c, D.r, D.ndofs);
+  if (!(r1 <= r0)) {
+    HIPCHK(hipMemcpyAsync(x, save, D.ndofs * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    c->learned_disabled = true;
+  }
+}
+
 // x_l = V(b_l) on level l (zero initial guess), Alg. 1.
 template <typename T>
 void vcycle(stmg_ctx* c, Hier<T>& H, int l) {
@@ -303,12 +382,12 @@ void vcycle(stmg_ctx* c, Hier<T>& H, int l) {
     return;
   }
   HIPCHK(launch_fill<T>(D.x, T(0), D.ndofs, c->stream));
-  op_smooth<T>(c, D, D.b, D.x, c->p.nu_pre, true);                       // presmoothing
+  op_smooth<T>(c, D, D.b, D.x, c->p.nu_pre, true, l);                    // presmoothing
   op_apply<T>(c, D, D.x, D.b, D.r, 1);                                   // residual
   op_restrict<T>(c, H, l, D.r, H.L[l + 1].b);                            // restriction
   vcycle<T>(c, H, l + 1);                                                // coarse-grid correction
   op_prolongate_add<T>(c, H, l, H.L[l + 1].x, D.x);                      // prolongation and correction
-  op_smooth<T>(c, D, D.b, D.x, c->p.nu_post, false);                     // postsmoothing
+  op_smooth<T>(c, D, D.b, D.x, c->p.nu_post, false, l);                  // postsmoothing
 }
 
 // z = V(v) for FP64 vectors v, z (device), in the context's precision
@@ -356,6 +435,16 @@ double dot(stmg_ctx* c, const double* a, const double* b, int64_t n) {
   HIPCHK(hipMemcpyAsync(&h, c->dh, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return h;
+}
+
+template <typename T>
+double norm2(stmg_ctx* c, const T* v, int64_t n) {
+  if constexpr (std::is_same<T, double>::value) {
+    return std::sqrt(dot(c, v, v, n));
+  } else {
+    HIPCHK(launch_cast_f2d(v, c->dtmp, n, c->stream));
+    return std::sqrt(dot(c, c->dtmp, c->dtmp, n));
+  }
 }
 
 bool valid_pow2(int v) { return v >= 1 && (v & (v - 1)) == 0; }
@@ -670,6 +759,7 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
     }
     const int m = c->cap - 1;
     c->history.clear();
+    c->learned_disabled = false;
     c->t_smooth.reset();
     c->t_vcyc.reset();
     c->t_op.reset();
@@ -762,6 +852,7 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
         info->t_operator_s = c->t_op.total_s();
         info->t_other_s = info->t_solve_s - tv - info->t_operator_s;
       }
+      info->learned_disabled = c->learned_disabled ? 1 : 0;
       info->history_len = (int)c->history.size();
       info->history = c->history.data();
     }
@@ -770,6 +861,144 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
   if (rc != STMG_OK) return (stmg_status)rc;
   if (status != STMG_OK) c->err = "FGMRES did not reach the tolerance within max_it";
   return (stmg_status)status;
+}
+
+stmg_status stmg_learned_load(stmg_ctx* c, const float* w, size_t n) {
+  if (!c || !w || n != (size_t)kNetParams) return STMG_EINVAL;
+  return (stmg_status)guarded(c, [&] {
+    net_alloc(c, 4096);
+    HIPCHK(hipMemcpyAsync(c->net.w, w, kNetParams * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(launch_fill<float>(c->net.m, 0.0f, kNetParams, c->stream));
+    HIPCHK(launch_fill<float>(c->net.v, 0.0f, kNetParams, c->stream));
+    HIPCHK(net_pack(c->net, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+stmg_status stmg_learned_weights(const stmg_ctx* cc, float* w, size_t n) {
+  stmg_ctx* c = const_cast<stmg_ctx*>(cc);
+  if (!c || !w || n != (size_t)kNetParams || !c->net_ready) return STMG_EINVAL;
+  return (stmg_status)guarded(c, [&] {
+    HIPCHK(hipMemcpyAsync(w, c->net.w, kNetParams * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+stmg_status stmg_learned_enable(stmg_ctx* c, int on) {
+  if (!c) return STMG_EINVAL;
+  if (on && !c->net_ready) {
+    c->err = "load weights before enabling the learned correction";
+    return STMG_EINVAL;
+  }
+  return (stmg_status)guarded(c, [&] {
+    if (on && c->lsave.empty()) {
+      for (size_t l = 0; l < c->host.size(); ++l) {
+        size_t bytes = (c->mixed ? sizeof(float) : sizeof(double));
+        c->lsave.push_back(c->pool.alloc<char>(c->host[l].ndofs * bytes));
+      }
+    }
+    c->learned_on = on != 0;
+  });
+}
+
+stmg_status stmg_learned_record(stmg_ctx* c, const double* b, const double* xstar, double* r_out, double* e_out) {
+  if (!c || !b || !xstar || !r_out || !e_out || c->host.size() < 2) return STMG_EINVAL;
+  if (c->mixed) { c->err = "record pairs with an FP64 context"; return STMG_EINVAL; }
+  if (!net_level(c->H64.L[0].a)) { c->err = "pairs need a 3D Q2/P1 x DG(1) finest level"; return STMG_EINVAL; }
+  return (stmg_status)guarded(c, [&] {
+    Hier<double>& H = c->H64;
+    DevLevel<double>& D = H.L[0];
+    const int64_t n = D.ndofs;
+    HIPCHK(hipMemcpyAsync(D.b, b, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(launch_fill<double>(D.x, 0.0, n, c->stream));
+    auto record = [&](int k) {
+      op_apply<double>(c, D, D.x, D.b, r_out + k * n, 1);
+      HIPCHK(hipMemcpyAsync(e_out + k * n, xstar, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(launch_axpy<double>(e_out + k * n, -1.0, D.x, n, c->stream));
+    };
+    op_smooth<double>(c, D, D.b, D.x, c->p.nu_pre, true);
+    record(0);
+    op_apply<double>(c, D, D.x, D.b, D.r, 1);
+    op_restrict<double>(c, H, 0, D.r, H.L[1].b);
+    vcycle<double>(c, H, 1);
+    op_prolongate_add<double>(c, H, 0, H.L[1].x, D.x);
+    op_smooth<double>(c, D, D.b, D.x, c->p.nu_post, false);
+    record(1);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+stmg_status stmg_learned_train(stmg_ctx* c, const float* rp, const float* ep, int n_pairs, uint64_t seed, int epochs,
+                               int batch, float lr, float* loss_hist) {
+  if (!c || !rp || !ep || n_pairs < 1 || epochs < 1 || batch < 8 || !(lr > 0) || !c->net_ready)
+    return STMG_EINVAL;
+  const LevelArgs& a = c->H64.L[0].a;
+  if (!net_level(a)) { c->err = "training needs a 3D Q2/P1 x DG(1) finest level"; return STMG_EINVAL; }
+  return (stmg_status)guarded(c, [&] {
+    net_alloc(c, batch);
+    if (batch > c->net.cap) throw Error(STMG_EINVAL, "batch too large");
+    const int64_t nd = c->host[0].ndofs;
+    const int64_t per = (int64_t)a.N * (a.Mp / a.C);
+    const int64_t nchunk = (per + batch - 1) / batch;
+    std::vector<int64_t> order((size_t)n_pairs * nchunk);
+    uint64_t st = seed * 6364136223846793005ULL + 1442695040888963407ULL;
+    auto rnd = [&]() {  // 64-bit LCG, top bits
+      st = st * 6364136223846793005ULL + 1442695040888963407ULL;
+      return st >> 11;
+    };
+    int t = 0;
+    size_t h = 0;
+    for (int ep_i = 0; ep_i < epochs; ++ep_i) {
+      for (size_t i = 0; i < order.size(); ++i) order[i] = (int64_t)i;
+      for (size_t i = order.size(); i > 1; --i) std::swap(order[i - 1], order[rnd() % i]);
+      for (int64_t job : order) {
+        const int64_t pair = job / nchunk, first = (job % nchunk) * batch;
+        const int64_t cnt = std::min<int64_t>(batch, per - first);
+        HIPCHK(net_inputs<float>(a, c->net, rp + pair * nd, ep + pair * nd, first, cnt, c->stream));
+        HIPCHK(net_forward(c->net, cnt, c->stream));
+        HIPCHK(net_loss(c->net, cnt, c->stream));
+        HIPCHK(net_backward(c->net, cnt, c->stream));
+        HIPCHK(net_adam(c->net, ++t, lr, c->stream));
+        double red[2];
+        HIPCHK(hipMemcpyAsync(red, c->net.red, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (loss_hist) loss_hist[h++] = red[1] > 0 ? (float)(red[0] / red[1]) : 0.0f;
+      }
+    }
+  });
+}
+
+stmg_status stmg_learned_correction(stmg_ctx* c, int level, const double* r, double* u) {
+  if (!c || !r || !u || level < 0 || level >= (int)c->host.size() || !c->net_ready) return STMG_EINVAL;
+  if (!net_level(c->H64.L[level].a)) return STMG_EINVAL;
+  return (stmg_status)guarded(c, [&] {
+    DevLevel<double>& D = c->H64.L[level];
+    HIPCHK(launch_fill<double>(u, 0.0, D.ndofs, c->stream));
+    net_correct<double>(c, D, r, u);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+stmg_status stmg_learned_gradient(stmg_ctx* c, int level, const double* r, const double* e, float* grad, double* loss) {
+  if (!c || !r || !e || !grad || level < 0 || level >= (int)c->host.size() || !c->net_ready) return STMG_EINVAL;
+  const LevelArgs& a = c->H64.L[level].a;
+  if (!net_level(a)) return STMG_EINVAL;
+  const int64_t total = (int64_t)a.N * (a.Mp / a.C);
+  if (total > c->net.cap) return STMG_EINVAL;
+  return (stmg_status)guarded(c, [&] {
+    net_alloc(c, total);
+    HIPCHK(net_inputs<double>(a, c->net, r, e, 0, total, c->stream));
+    HIPCHK(net_forward(c->net, total, c->stream));
+    HIPCHK(net_loss(c->net, total, c->stream));
+    HIPCHK(net_backward(c->net, total, c->stream));
+    std::vector<float> g(kNetParams);
+    double red[2];
+    HIPCHK(hipMemcpyAsync(g.data(), c->net.g, kNetParams * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(red, c->net.red, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < kNetParams; ++i) grad[i] = (float)(g[i] / red[1]);
+    if (loss) *loss = red[0] / red[1];
+  });
 }
 
 }  // extern "C"

@@ -65,7 +65,17 @@ _sig = {
     "stmg_vcycle": [_P, _P, _P],
     "stmg_solve": [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.POINTER(SolveInfo)],
     "stmg_project_pressure_mean_zero": [_P, _P],
+    "stmg_learned_load": [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t],
+    "stmg_learned_weights": [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t],
+    "stmg_learned_enable": [_P, ctypes.c_int],
+    "stmg_learned_record": [_P, _P, _P, _P, _P],
+    "stmg_learned_train": [_P, _P, _P, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                           ctypes.POINTER(ctypes.c_float)],
+    "stmg_learned_correction": [_P, ctypes.c_int, _P, _P],
+    "stmg_learned_gradient": [_P, ctypes.c_int, _P, _P, ctypes.POINTER(ctypes.c_float),
+                              ctypes.POINTER(ctypes.c_double)],
 }
+NET_PARAMS = 52704
 for _name, _args in _sig.items():
     _f = getattr(lib, _name)
     _f.argtypes = _args
@@ -207,6 +217,63 @@ class Solver:
 
     def project_pressure(self, x):
         _check(lib.stmg_project_pressure_mean_zero(self.ctx, _ptr(x, self.ndofs(0))), self.ctx)
+
+    # ---------------------------------------------------------- learned
+    def learned_load(self, weights):
+        import numpy as np
+        w = np.ascontiguousarray(weights, dtype=np.float32).ravel()
+        if w.size != NET_PARAMS:
+            raise ValueError(f"expected {NET_PARAMS} weights")
+        _check(lib.stmg_learned_load(self.ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size), self.ctx)
+
+    def learned_weights(self):
+        import numpy as np
+        w = np.zeros(NET_PARAMS, dtype=np.float32)
+        _check(lib.stmg_learned_weights(self.ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size),
+               self.ctx)
+        return w
+
+    def learned_enable(self, on=True):
+        _check(lib.stmg_learned_enable(self.ctx, int(on)), self.ctx)
+
+    def learned_record(self, b, xstar):
+        n = self.ndofs(0)
+        r = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+        e = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+        _check(lib.stmg_learned_record(self.ctx, _ptr(b, n), _ptr(xstar, n), ctypes.c_void_p(r.data_ptr()),
+                                       ctypes.c_void_p(e.data_ptr())), self.ctx)
+        return r.view(2, n), e.view(2, n)
+
+    def learned_train(self, r_pairs, e_pairs, seed=0, epochs=1, batch=4096, lr=1e-3):
+        import numpy as np
+        for t in (r_pairs, e_pairs):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2:
+                raise TypeError("pairs must be contiguous float32 CUDA tensors of shape (n_pairs, n_dofs)")
+        n_pairs = r_pairs.shape[0]
+        d, n, r, k, N = (self.params.dim, self.params.n_cells_1d, self.params.r, self.params.k, self.params.n_sub)
+        cells = N * n ** d
+        steps = epochs * n_pairs * ((cells + batch - 1) // batch)
+        hist = np.zeros(steps, dtype=np.float32)
+        _check(lib.stmg_learned_train(self.ctx, ctypes.c_void_p(r_pairs.data_ptr()), ctypes.c_void_p(e_pairs.data_ptr()),
+                                      n_pairs, seed, epochs, batch, lr,
+                                      hist.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), self.ctx)
+        return hist
+
+    def learned_correction(self, r, level=0):
+        n = self.ndofs(level)
+        u = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(lib.stmg_learned_correction(self.ctx, level, _ptr(r, n), _ptr(u, n)), self.ctx)
+        return u
+
+    def learned_gradient(self, r, e, level=0):
+        import numpy as np
+        n = self.ndofs(level)
+        g = np.zeros(NET_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(lib.stmg_learned_gradient(self.ctx, level, _ptr(r, n), _ptr(e, n),
+                                         g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(loss)),
+               self.ctx)
+        return g, loss.value
 
     def solve(self, b, x, rtol=1e-8, max_it=100, raise_on_noconv=True):
         n = self.ndofs(0)

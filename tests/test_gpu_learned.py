@@ -1,0 +1,133 @@
+"""GPU checks of the learned correction (BF16 on the matrix cores, FP32
+accumulation) against the FP64 oracle network, the switch-off rule, and what
+a trained network gains over plain multigrid."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import announce, dev, host
+from stmg_inputs import random_rhs
+
+pytestmark = pytest.mark.gpu
+
+CFG = dict(dim=3, n_cells_1d=4, n_coarse_1d=2, r=1, k=1, n_sub=2, deform_amp=0.03, k_min=1, tau=0.05, nu=1.0,
+           omega=0.8)
+
+
+@pytest.fixture(scope="module")
+def small():
+    from oracle.assembly import SpatialLevel
+    from oracle.spacetime import SpaceTimeLevel
+    from paper_2502_09159_amd import stmg
+    g = stmg.Solver(**CFG)
+    L = SpaceTimeLevel(SpatialLevel(3, 4, 1, 0.03, 1.0), 1, 2, 0.05)
+    yield g, L
+    g.close()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_correction_matches_oracle(small):
+    from oracle import learned as ln
+    from paper_2502_09159_amd.learned import he_init
+    g, L = small
+    w = he_init(3)
+    g.learned_load(w)
+    rng = np.random.default_rng(31)
+    r = rng.standard_normal(L.ndofs)
+    u = host(g.learned_correction(dev(r)))
+    ref = ln.correction(L, ln.unpack(w.astype(np.float64)), r)
+    err = rel_l2(u, ref)
+    announce(f"learned correction vs oracle: rel L2 {err:.2e}")
+    assert err < 3e-2
+
+
+def test_gradient_matches_oracle(small):
+    from oracle import learned as ln
+    from paper_2502_09159_amd.learned import he_init
+    g, L = small
+    w = he_init(5)
+    g.learned_load(w)
+    rng = np.random.default_rng(32)
+    r = rng.standard_normal(L.ndofs)
+    e = rng.standard_normal(L.ndofs)
+    grad, loss = g.learned_gradient(dev(r), dev(e))
+    Ws = ln.unpack(w.astype(np.float64))
+    Xn, mask, s = ln.net_inputs(L, r)
+    tv, tp = ln.targets(L, e, s)
+    loss_ref, grads = ln.loss_and_grads(Ws, Xn, mask, tv, tp)
+    assert abs(loss - loss_ref) < 2e-2 * loss_ref
+    off = 0
+    for layer, gr in enumerate(grads):
+        n = gr.size
+        err = rel_l2(grad[off:off + n].astype(np.float64), gr.ravel())
+        announce(f"layer {layer + 1} weight gradient vs oracle: rel L2 {err:.2e}")
+        assert err < 5e-2
+        off += n
+
+
+def test_switch_off_on_a_bad_network():
+    """A network that raises the residual is undone and switched off; the
+    solve then matches plain multigrid exactly."""
+    from paper_2502_09159_amd import stmg
+    from paper_2502_09159_amd.learned import he_init
+    cfg = dict(CFG, n_cells_1d=8)
+    g = stmg.Solver(**cfg)
+    try:
+        b = dev(random_rhs(3, 8, 1, 1, 2, 41))
+        x0 = torch.empty_like(b)
+        plain = g.solve(b, x0, rtol=1e-8)
+        g.learned_load(he_init(7) * 50.0)
+        g.learned_enable(True)
+        x1 = torch.empty_like(b)
+        info = g.solve(b, x1, rtol=1e-8)
+        announce(f"bad net: disabled={info['learned_disabled']} it={info['iterations']} plain={plain['iterations']}")
+        assert info["learned_disabled"] == 1
+        assert info["iterations"] == plain["iterations"]
+        assert (torch.linalg.norm(x1 - x0) / torch.linalg.norm(x0)).item() < 1e-12
+    finally:
+        g.close()
+
+
+def test_training_and_gain():
+    """Train on pairs from random forcings (8^3, Q2/P1 x DG(1), 2 subintervals),
+    check the loss falls below the untrained network's on held-out pairs, and
+    report iterations and time to 1e-8 with the trained net, an untrained
+    net and none (the gain is measured, not assumed)."""
+    from paper_2502_09159_amd import learned, stmg
+    cfg = dict(CFG, n_cells_1d=8)
+    g = stmg.Solver(**cfg)
+    try:
+        train_b = [random_rhs(3, 8, 1, 1, 2, s) for s in range(1000, 1040)]
+        test_b = [random_rhs(3, 8, 1, 1, 2, s) for s in range(2000, 2004)]
+        rp, ep = learned.make_pairs(g, train_b)
+        rt, et = learned.make_pairs(g, test_b)
+        w0 = learned.he_init(0)
+        g.learned_load(w0)
+        loss0 = np.mean([g.learned_gradient(rt[i].double().contiguous(), et[i].double().contiguous())[1]
+                         for i in range(rt.shape[0])])
+        w, hist = learned.train(g, rp, ep, seed=1, epochs=6, batch=512, lr=1e-3)
+        loss1 = np.mean([g.learned_gradient(rt[i].double().contiguous(), et[i].double().contiguous())[1]
+                         for i in range(rt.shape[0])])
+        announce(f"held-out loss untrained {loss0:.3f} -> trained {loss1:.3f}; train loss first {hist[:20].mean():.3f} "
+                 f"last {hist[-20:].mean():.3f}")
+        assert np.all(np.isfinite(hist))
+        assert loss1 < loss0
+        b = dev(random_rhs(3, 8, 1, 1, 2, 4))
+        res = {}
+        for name, wts in (("none", None), ("untrained", w0), ("trained", w)):
+            x = torch.empty_like(b)
+            if wts is None:
+                g.learned_enable(False)
+            else:
+                g.learned_load(wts)
+                g.learned_enable(True)
+            info = g.solve(b, x, rtol=1e-8)
+            res[name] = (info["iterations"], info["t_solve_s"], info["learned_disabled"], info["rel_residual"])
+            assert info["rel_residual"] <= 1e-8
+        announce("gain (iterations, seconds, disabled): " + str(res))
+        g.learned_enable(False)
+    finally:
+        g.close()
