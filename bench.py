@@ -1,5 +1,6 @@
 """Benchmark: space-time DoF/s to a 1e-8 relative residual, FGMRES with the
-hp space-time multigrid V-cycle (plain FP64 vs FP32 V-cycle), one MI355X.
+hp space-time multigrid V-cycle, one MI355X: the FP32 V-cycle with the
+learned correction (value) against plain FP64 multigrid (reported beside it).
 
 One step = one complete solve of the slab system (FGMRES to ||b - S x|| <=
 1e-8 ||b||, explicitly rechecked) with b resident in HBM and the set-up done.
@@ -32,6 +33,7 @@ WORKLOADS = {
                                 "nu(x)=exp(0.5 g(x))"),
 }
 TAU, OMEGA = 0.05, 0.8
+WEIGHTS = os.path.join(ROOT, "paper_2502_09159_amd", "weights", "net_c4.npy")
 
 
 def solver_params(w, precision):
@@ -88,8 +90,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--variant", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
+    ap.add_argument("--variant", default="learned", choices=["learned", "mixed", "fp64"])
+    ap.add_argument("--weights", default=WEIGHTS, help="trained network (from paper_2502_09159_amd.train_c4)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--k-min", type=int, default=None, help="override the temporal p-coarsening floor")
@@ -108,9 +111,12 @@ def main():
     if args.k_min is not None:
         w["k_min"] = args.k_min
     nu_fn = FourierViscosity(w["nu_seed"]) if "nu_seed" in w else None
-    prec = stmg.MIXED_FP32 if args.variant == "mixed" else stmg.FP64
+    prec = stmg.FP64 if args.variant == "fp64" else stmg.MIXED_FP32
     t0 = time.perf_counter()
     S = stmg.Solver(nu_fn=nu_fn, **solver_params(w, prec))
+    if args.variant == "learned":
+        S.learned_load(np.load(args.weights, allow_pickle=False))
+        S.learned_enable(True)
     setup_s = time.perf_counter() - t0
     print(f"[bench] setup {args.workload} {args.variant}: {setup_s:.1f} s", file=sys.stderr, flush=True)
     ndofs = S.ndofs(0)
@@ -121,11 +127,12 @@ def main():
         print(f"[bench] warmup {i}: {info['iterations']} it, {info['t_solve_s']*1e3:.1f} ms",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    its = []
+    its, disabled = [], []
     t0 = time.perf_counter()
     for i in range(args.steps):
         info = S.solve(b, x, rtol=1e-8, max_it=200)
         its.append(info["iterations"])
+        disabled.append(info["learned_disabled"])
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     ms_per_step = 1e3 * t / args.steps
@@ -153,7 +160,21 @@ def main():
     op_ms = S.kernel_time(1, level=0, reps=reps)
 
     extra = {}
-    if not args.no_compare and args.variant == "mixed":
+    if args.variant == "learned":
+        extra["learned_switched_off"] = disabled
+    if not args.no_compare and args.variant == "learned":
+        # the same FP32 context with the network off
+        S.learned_enable(False)
+        x32 = torch.empty_like(b)
+        S.solve(b, x32, rtol=1e-8, max_it=200)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info32 = S.solve(b, x32, rtol=1e-8, max_it=200)
+        torch.cuda.synchronize()
+        t32 = time.perf_counter() - t0
+        S.learned_enable(True)
+        extra.update({"fp32_plain_dofs_per_s": ndofs / t32, "fp32_plain_iterations": info32["iterations"]})
+    if not args.no_compare and args.variant != "fp64":
         S64 = stmg.Solver(nu_fn=nu_fn, **solver_params(w, stmg.FP64))
         x64 = torch.empty_like(b)
         info64 = S64.solve(b, x64, rtol=1e-8, max_it=200)
@@ -162,17 +183,19 @@ def main():
         info64 = S64.solve(b, x64, rtol=1e-8, max_it=200)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
-        extra = {"fp64_dofs_per_s": ndofs / t64, "fp64_iterations": info64["iterations"],
-                 "speedup_vs_fp64": (ndofs / (t / args.steps)) / (ndofs / t64),
-                 "rel_err_vs_fp64": (torch.linalg.norm(x - x64) / torch.linalg.norm(x64)).item()}
+        extra.update({"fp64_dofs_per_s": ndofs / t64, "fp64_iterations": info64["iterations"],
+                      "speedup_vs_fp64": (ndofs / (t / args.steps)) / (ndofs / t64),
+                      "rel_err_vs_fp64": (torch.linalg.norm(x - x64) / torch.linalg.norm(x64)).item()})
         S64.close()
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     line = {
         "metric": METRIC, "value": value, "unit": "space-time DoF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64" if prec == stmg.MIXED_FP32 else "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": {"learned": "f32+bf16+f64", "mixed": "f32+f64", "fp64": "f64"}[args.variant],
+        "data": "synthetic",
         "config": {"workload": w["label"], "ndofs": ndofs, "variant": args.variant,
-                   "solver": "FGMRES(CGS2) + hp space-time MG V-cycle, cell Vanka (1 pre/1 post), omega 0.8",
+                   "solver": "FGMRES(CGS2) + hp space-time MG V-cycle, cell Vanka (1 pre/1 post), omega 0.8"
+                             + (", learned correction on Q2/P1 x DG(1) levels" if args.variant == "learned" else ""),
                    "iterations": its[-1], "setup_s": round(setup_s, 2),
                    "operator_residual_ms": round(op_ms, 4), **extra},
         "roofline": roofline, "cpu_baseline": cpu,

@@ -190,8 +190,10 @@ stmg_status stmg_project_pressure_mean_zero(stmg_ctx* ctx, double* x);
  * s_T) to a correction (6 velocity channels at the nodes, 8 pressure values
  * averaged over the nodes; times s_T), summed over cells with the valence
  * weighting of the Vanka patches.  BF16 operands on the matrix cores, FP32
- * accumulation.  If a correction raises the residual 2-norm on its level it
- * is undone and the network is switched off for the rest of the solve.
+ * accumulation.  The correction c is added with the step alpha = <r, S c> /
+ * <S c, S c> that minimises the level's residual 2-norm, so it cannot raise
+ * it; if alpha <= 0 the correction is skipped and the network is switched
+ * off for the rest of the solve.
  * Weights: STMG_NET_PARAMS FP32 values, W1 (32x15x27), W2 (32x32x27),
  * W3 (14x32x27), each [c_out][c_in][offset], offset (dx+1)+3(dy+1)+9(dz+1).
  * ------------------------------------------------------------------------ */

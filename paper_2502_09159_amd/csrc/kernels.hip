@@ -994,6 +994,25 @@ hipError_t launch_multidot(const double* V, int64_t ldv, int nv, const double* w
   return hipGetLastError();
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_dot_t(const T* __restrict__ a, const T* __restrict__ b, int64_t n,
+                                               double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += (double)a[i] * (double)b[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+template <typename T>
+hipError_t launch_dot(const T* a, const T* b, int64_t n, double* partial, double* out, hipStream_t s) {
+  k_dot_t<T><<<kDotBlocks, 256, 0, s>>>(a, b, n, partial);
+  k_dot_final<<<1, 64, 0, s>>>(partial, 1, out);
+  return hipGetLastError();
+}
+template hipError_t launch_dot<double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
+template hipError_t launch_dot<float>(const float*, const float*, int64_t, double*, double*, hipStream_t);
+
 __global__ void k_multi_axpy(double* __restrict__ w, const double* __restrict__ V, int64_t ldv, int nv,
                              const double* __restrict__ h, int64_t n, double sign) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

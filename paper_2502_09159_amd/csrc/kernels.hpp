@@ -77,6 +77,10 @@ hipError_t launch_cast_f2d(const float* a, double* b, int64_t n, hipStream_t s);
 // partial buffer needs nv * 1024 doubles.
 hipError_t launch_multidot(const double* V, int64_t ldv, int nv, const double* w, int64_t n, double* partial,
                            double* out, hipStream_t s);
+// out[0] = a . b for vectors of type T (FP64 accumulation, fixed order);
+// partial needs 1024 doubles.
+template <typename T>
+hipError_t launch_dot(const T* a, const T* b, int64_t n, double* partial, double* out, hipStream_t s);
 // w -= sum_i h_i V_i (h on device)
 hipError_t launch_multi_axpy(double* w, const double* V, int64_t ldv, int nv, const double* h, int64_t n,
                              hipStream_t s);

@@ -354,22 +354,34 @@ void net_correct(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x) {
 template <typename T>
 double norm2(stmg_ctx* c, const T* v, int64_t n);
 
-// After a Vanka sweep: r = b - S x, x' = x + net(r); keep x' only if the
-// residual 2-norm on this level does not grow, otherwise undo and switch off.
+// After a Vanka sweep: r = b - S x, c = net(r), w = S c and x += alpha c with
+// the residual-minimising alpha = <r, w> / <w, w>, so the level residual
+// cannot grow.  If the direction does not reduce it (alpha <= 0) the
+// correction is skipped and switched off for the rest of the solve.
+template <typename T>
+double dot_t(stmg_ctx* c, const T* a, const T* b, int64_t n) {
+  HIPCHK(launch_dot<T>(a, b, n, c->partial, c->dh, c->stream));
+  double h;
+  HIPCHK(hipMemcpyAsync(&h, c->dh, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return h;
+}
+
 template <typename T>
 void learned_step(stmg_ctx* c, DevLevel<T>& D, int level, const T* b, T* x) {
   if (!c->learned_on || c->learned_disabled || !c->net_ready || !net_level(D.a)) return;
+  T* cv = static_cast<T*>(c->lsave[2 * level]);
+  T* wv = static_cast<T*>(c->lsave[2 * level + 1]);
   op_apply<T>(c, D, x, b, D.r, 1);
-  const double r0 = norm2<T>(c, D.r, D.ndofs);
-  T* save = static_cast<T*>(c->lsave[level]);
-  HIPCHK(hipMemcpyAsync(save, x, D.ndofs * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
-  net_correct<T>(c, D, D.r, x);
-  op_apply<T>(c, D, x, b, D.r, 1);
-  const double r1 = norm2<T>(c, D.r, D.ndofs);
-  if (!(r1 <= r0)) {
-    HIPCHK(hipMemcpyAsync(x, save, D.ndofs * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(launch_fill<T>(cv, T(0), D.ndofs, c->stream));
+  net_correct<T>(c, D, D.r, cv);
+  op_apply<T>(c, D, cv, cv, wv, 0);
+  const double rw = dot_t<T>(c, D.r, wv, D.ndofs), ww = dot_t<T>(c, wv, wv, D.ndofs);
+  if (!(rw > 0.0) || !(ww > 0.0) || !std::isfinite(rw / ww)) {
     c->learned_disabled = true;
+    return;
   }
+  HIPCHK(launch_axpy<T>(x, (T)(rw / ww), cv, D.ndofs, c->stream));
 }
 
 // x_l = V(b_l) on level l (zero initial guess), Alg. 1.
@@ -894,7 +906,9 @@ stmg_status stmg_learned_enable(stmg_ctx* c, int on) {
     if (on && c->lsave.empty()) {
       for (size_t l = 0; l < c->host.size(); ++l) {
         size_t bytes = (c->mixed ? sizeof(float) : sizeof(double));
-        c->lsave.push_back(c->pool.alloc<char>(c->host[l].ndofs * bytes));
+        bool use = net_level(c->H64.L[l].a);
+        c->lsave.push_back(use ? c->pool.alloc<char>(c->host[l].ndofs * bytes) : nullptr);
+        c->lsave.push_back(use ? c->pool.alloc<char>(c->host[l].ndofs * bytes) : nullptr);
       }
     }
     c->learned_on = on != 0;

@@ -55,25 +55,37 @@ class FourierViscosity:
     """nu(x) = exp(0.5 g(x)), g a random smooth Fourier series on [0,1]^3:
     g = sum_{m in {0..7}^3 \\ 0} (a_m cos 2 pi m.x + b_m sin 2 pi m.x) (1+|m|^2)^{-3/2},
     a, b ~ N(0,1) from the seed, rescaled so that max |g| = 1 over a 48^3 grid
-    of the unit cube (so nu lies in about [e^-0.5, e^0.5])."""
+    of the unit cube (so nu lies in about [e^-0.5, e^0.5]).  Evaluated as
+    Re sum_m (a_m - i b_m) e^{2 pi i m.x}, contracted one axis at a time."""
 
     def __init__(self, seed, modes=8):
         rng = np.random.Generator(np.random.PCG64(seed))
         m = np.array([(i, j, l) for i in range(modes) for j in range(modes) for l in range(modes)
-                      if (i, j, l) != (0, 0, 0)], dtype=float)
-        self.m = m
+                      if (i, j, l) != (0, 0, 0)], dtype=int)
+        self.modes = modes
         damp = (1.0 + np.sum(m * m, axis=1)) ** -1.5
-        self.a = rng.standard_normal(len(m)) * damp
-        self.b = rng.standard_normal(len(m)) * damp
+        a = rng.standard_normal(len(m)) * damp
+        b = rng.standard_normal(len(m)) * damp
+        self.C = np.zeros((modes, modes, modes), dtype=complex)
+        self.C[m[:, 0], m[:, 1], m[:, 2]] = a - 1j * b
+        self.scale = 1.0
         g = np.linspace(0.0, 1.0, 48)
         pts = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
-        self.scale = 1.0
-        gmax = np.max(np.abs(self._g(pts)))
-        self.scale = 1.0 / gmax
+        self.scale = 1.0 / np.max(np.abs(self._g(pts)))
 
     def _g(self, x):
-        ph = 2.0 * np.pi * (np.asarray(x, float) @ self.m.T)
-        return self.scale * (np.cos(ph) @ self.a + np.sin(ph) @ self.b)
+        x = np.asarray(x, float)
+        out = np.empty(len(x))
+        k = np.arange(self.modes)
+        M = self.modes
+        C0 = self.C.reshape(M, M * M)
+        for s in range(0, len(x), 1 << 16):
+            xs = x[s:s + (1 << 16)]
+            E = [np.exp(2j * np.pi * xs[:, d])[:, None] ** k for d in range(3)]   # (P, M)
+            t = (E[0] @ C0).reshape(-1, M, M)                                     # sum over m1
+            t = np.einsum("pj,pjk->pk", E[1], t)                                  # sum over m2
+            out[s:s + (1 << 16)] = self.scale * np.einsum("pk,pk->p", E[2], t).real
+        return out
 
     def __call__(self, x):
         return np.exp(0.5 * self._g(x))

@@ -68,9 +68,11 @@ def test_gradient_matches_oracle(small):
         off += n
 
 
-def test_switch_off_on_a_bad_network():
-    """A network that raises the residual is undone and switched off; the
-    solve then matches plain multigrid exactly."""
+@pytest.mark.parametrize("kind", ["nan", "zero"])
+def test_switch_off_on_a_bad_network(kind):
+    """A network whose correction cannot reduce the residual (non-finite or
+    zero output) is switched off at its first application; the solve then
+    matches plain multigrid exactly."""
     from paper_2502_09159_amd import stmg
     from paper_2502_09159_amd.learned import he_init
     cfg = dict(CFG, n_cells_1d=8)
@@ -79,11 +81,15 @@ def test_switch_off_on_a_bad_network():
         b = dev(random_rhs(3, 8, 1, 1, 2, 41))
         x0 = torch.empty_like(b)
         plain = g.solve(b, x0, rtol=1e-8)
-        g.learned_load(he_init(7) * 50.0)
+        w = he_init(7)
+        w[:] = np.nan if kind == "nan" else 0.0
+        g.learned_load(w)
         g.learned_enable(True)
         x1 = torch.empty_like(b)
         info = g.solve(b, x1, rtol=1e-8)
-        announce(f"bad net: disabled={info['learned_disabled']} it={info['iterations']} plain={plain['iterations']}")
+        g.learned_enable(False)
+        announce(f"{kind} net: disabled={info['learned_disabled']} it={info['iterations']} "
+                 f"plain={plain['iterations']}")
         assert info["learned_disabled"] == 1
         assert info["iterations"] == plain["iterations"]
         assert (torch.linalg.norm(x1 - x0) / torch.linalg.norm(x0)).item() < 1e-12
