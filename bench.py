@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison solve")
     ap.add_argument("--k-min", type=int, default=None, help="override the temporal p-coarsening floor")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (multi-GPU sharding is a design, not built)",
@@ -107,6 +109,12 @@ def main():
     from paper_2502_09159_amd import stmg
     from stmg_inputs import FourierViscosity, random_rhs
 
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = dict(WORKLOADS[args.workload])
     if args.k_min is not None:
         w["k_min"] = args.k_min

@@ -1,7 +1,7 @@
 """Summarise a rocprofv3 kernel-trace database (rocpd SQLite) per kernel:
 calls, total and average duration, share of GPU time, VGPR/scratch use.
 
-Usage: python profiles/summarize_rocpd.py <results.db> [title]
+Usage: python -m paper_2502_09159_amd.prof_summary <results.db> [title]
 """
 import sqlite3
 import sys
