@@ -270,6 +270,41 @@ static double inv_det(int d, const double* J, double* Ji) {
   return det;
 }
 
+int apply_geometry_count(int d) { return 1 + d * d + d * (d + 1) / 2; }
+
+void apply_geometry(const LevelHost& L, std::vector<double>& geo) {
+  const int d = L.d, Q = L.Q, NG = apply_geometry_count(d), ZP = d == 3 ? Q : 1;
+  geo.assign((size_t)L.ncells * NG * 16 * ZP, 0.0);
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < L.ncells; ++c) {
+    double J[9], Ji[9], X[3], xi[3];
+    for (int z = 0; z < ZP; ++z)
+      for (int py = 0; py < Q; ++py)
+        for (int px = 0; px < Q; ++px) {
+          const int pi[3] = {px, py, z};
+          double wq = 1.0;
+          for (int j = 0; j < d; ++j) { xi[j] = L.st.gx[pi[j]]; wq *= L.st.gw[pi[j]]; }
+          cell_jacobian(L, c, xi, X, J);
+          const double det = inv_det(d, J, Ji);
+          const double jxw = det * wq;
+          const int p = px + Q * py + Q * Q * z;
+          const double nu = L.nu_q.empty() ? L.nu_const : L.nu_q[(size_t)c * L.nloc + p];
+          double f[16];
+          f[0] = jxw;
+          for (int j = 0; j < d; ++j)
+            for (int i = 0; i < d; ++i) f[1 + j * d + i] = jxw * Ji[j * d + i];
+          int o = 1 + d * d;
+          for (int j = 0; j < d; ++j)
+            for (int k = j; k < d; ++k) {
+              double s = 0.0;
+              for (int i = 0; i < d; ++i) s += Ji[j * d + i] * Ji[k * d + i];
+              f[o++] = nu * jxw * s;
+            }
+          for (int g = 0; g < NG; ++g) geo[(((size_t)c * NG + g) * 16 + px + 4 * py) * ZP + z] = f[g];
+        }
+  }
+}
+
 void build_level(const Params& P, const LevelSpec& s, LevelHost& L) {
   L.d = P.d; L.n = s.n; L.r = s.r; L.k = s.k; L.N = s.N;
   L.tau = P.tau * P.N / s.N;

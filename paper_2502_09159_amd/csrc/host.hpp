@@ -90,6 +90,14 @@ struct Params {
 // Geometry and element matrices of one level.
 void build_level(const Params& P, const LevelSpec& s, LevelHost& L);
 
+// Geometry of the operator kernel at the Gauss points of every cell:
+// value 0: JxW; 1 + j d + i: JxW Jinv[j][i]; then nu JxW (Jinv Jinv^T)[j][j']
+// for j <= j' row by row (apply_geometry_count(d) values).  Layout
+// [cell][value][x + 4 y][z]: x and y padded to 4, z < Q in 3D and a single z
+// in 2D; padding entries are zero.
+int apply_geometry_count(int d);
+void apply_geometry(const LevelHost& L, std::vector<double>& geo);
+
 // Smoother factors of one level (Schur-factored local inverse):
 // As_inv: ncells x m x m (col-major), m = (k+1) nloc, local velocity order (a, i)
 // Bm    : ncells x C x d x nloc, Dirichlet columns zeroed

@@ -54,308 +54,502 @@ __device__ __forceinline__ int64_t gnode(const LevelArgs& L, const int* cc, int 
   return g;
 }
 
-// One 1D contraction along `dir` through LDS: out(p) = sum_t M[pd][t] buf(p|pd=t)
-// (trans: M[t][pd]).
-template <typename T, int Q>
-__device__ __forceinline__ T contract(const T* buf, int p, int dir, const T* M, bool trans) {
-  const int stride = dir == 0 ? 1 : (dir == 1 ? Q : Q * Q);
-  const int pd = (p / stride) % Q;
-  const T* b = buf + (p - pd * stride);
-  T s = 0;
-#pragma unroll
-  for (int t = 0; t < Q; ++t) s += (trans ? M[t * Q + pd] : M[pd * Q + t]) * b[t * stride];
-  return s;
+// Work groups are dispatched round-robin over the 8 XCDs (each with its own
+// L2); remap the hardware block id so that every XCD works on one contiguous
+// range of logical blocks (neighbouring cells share cache lines).
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid64, int64_t nblocks64) {
+  const unsigned bid = (unsigned)bid64, nblocks = (unsigned)nblocks64;  // grids stay below 2^32 blocks
+  const unsigned q = nblocks >> 3, rem = nblocks & 7;
+  const unsigned xcd = bid & 7, local = bid >> 3;
+  return xcd < rem ? xcd * (q + 1) + local : rem * (q + 1) + (xcd - rem) * q + local;
 }
 
 }  // namespace
 
 // =====================================================================
-// Space-time operator.  One work item = (cell of one colour, subinterval n);
-// one thread per quadrature point (Q^d <= 64), 64 / Q^d cells per wave.
-// For every temporal dof a of subinterval n:
+// Space-time operator (Eq. (GloSys) with Eq. (InAlg), (DefDtauh); M^tau
+// diagonal).  For every temporal dof a of subinterval n:
 //   y_v += K_ab M x_v[n,b] + c_a A_nu x_v[n,a] - c_a B^T x_p[n,a] - phi_a(-1) M x_v[n-1,k]
-//   y_p += -c_a B x_v[n,a]
-// with c_a = (tau/2) w_a (Eq. (InAlg), (DefDtauh), (GloSys); M^tau diagonal).
+//   y_p += -c_a B x_v[n,a],      c_a = (tau/2) w_a.
+// Mapping onto a wave: one cell per row of 16 lanes (a 4x4 grid of (x, y)
+// node / Gauss-point positions, padded with zeros when Q = 3), the z
+// direction held in registers (a pencil of Q values), four cells per wave.
+// Sum-factorized 1D contractions run along x with quad-permute DPP, along y
+// with row-rotate DPP and along z in registers: the loop has no LDS traffic
+// besides small coefficient reads and no barriers.  A wave walks through the
+// subintervals of its chunk and carries the end value of the previous
+// subinterval (the jump term) in registers.  Geometry per Gauss point is
+// precomputed: JxW, JxW J^{-1} and nu JxW J^{-1} J^{-T}.
+// Velocity contributions go to the cell-local scratch E (summed per node by
+// k_apply_gather in a fixed order); pressure rows are written directly.
 // =====================================================================
-template <typename T, int D, int Q>
-__global__ __launch_bounds__(64) void k_apply(LevelArgs L, const double* __restrict__ verts,
-                                              const T* __restrict__ nu_q, T nu_const, const T* __restrict__ tab,
-                                              const T* __restrict__ x, const T* __restrict__ b,
-                                              T* __restrict__ y, T* __restrict__ E, int mode) {
-  constexpr int NL = D == 2 ? Q * Q : Q * Q * Q;
-  constexpr int CPB = 64 / NL;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* smem = reinterpret_cast<T*>(smem_raw);
-  const int nt = L.nt, C = L.C;
-  const int tabn = 2 * Q * Q + 2 * Q + nt * nt + 2 * nt + NL * C;
-  for (int t = threadIdx.x; t < tabn; t += blockDim.x) smem[t] = tab[t];
-  const T* sS = smem;
-  const T* sDg = sS + Q * Q;
-  const T* sgx = sDg + Q * Q;
-  const T* sgw = sgx + Q;
-  const T* sK = sgw + Q;
-  const T* sphi = sK + nt * nt;
-  const T* scoef = sphi + nt;
-  const T* spsi = scoef + nt;
-  const int per_cell = 5 * NL + nt * C;
-  T* cbase = smem + ((tabn + 1) & ~1);
+namespace {
 
-  const int tid = threadIdx.x;
-  int slot = tid / NL;
-  const int p = tid % NL;
-  const int64_t total = L.Mp / L.C;
-  const int64_t w = (int64_t)blockIdx.x * CPB + slot;
-  bool active = slot < CPB && w < total;
-  const T sgn = mode ? T(-1) : T(1);
-  if (slot > CPB) slot = CPB;
-  T* bufA = cbase + slot * per_cell;
-  T* bufB = bufA + NL;
-  T* g0 = bufB + NL;
-  T* g1 = g0 + NL;
-  T* g2 = g1 + NL;
-  T* pv = g2 + NL;
-  const int n = blockIdx.y;
+// DPP lane permutations, each a bijection inside a group of 4 lanes (quad
+// rotations) or inside a row of 16 lanes (rotations by multiples of 4).  The
+// source lane of every permutation is read back on the device once per block,
+// so the contraction coefficients never depend on the rotation direction.
+constexpr int kQuadRot1 = 0x39, kQuadRot2 = 0x4E, kQuadRot3 = 0x93;
+constexpr int kRowRot1 = 0x12C, kRowRot2 = 0x128, kRowRot3 = 0x124;
+constexpr int kQuadSwap1 = 0xB1;
 
-  const int64_t cell = active ? w : 0;
-  int cc[3] = {(int)(cell % L.n), (int)((cell / L.n) % L.n), D == 3 ? (int)(cell / ((int64_t)L.n * L.n)) : 0};
-  bool fr;
-  int val;
-  const int64_t g = gnode<D>(L, cc, p, fr, val);
-  const int pq[3] = {p % Q, (p / Q) % Q, p / (Q * Q)};
-  __syncthreads();
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)dpp_i<CTRL>((int)(unsigned)u);
+  const unsigned hi = (unsigned)dpp_i<CTRL>((int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
 
-  // ---- geometry at this quadrature point: J of the multilinear map
-  T J[D][D];
-#pragma unroll
-  for (int i = 0; i < D; ++i)
-#pragma unroll
-    for (int j = 0; j < D; ++j) J[i][j] = 0;
-  T xi[D];
-#pragma unroll
-  for (int j = 0; j < D; ++j) xi[j] = sgx[pq[j]];
-#pragma unroll
-  for (int v = 0; v < (1 << D); ++v) {
-    int64_t vi = 0, st = 1;
-    T f[D], df[D];
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      int bit = (v >> j) & 1;
-      vi += (cc[j] + bit) * st;
-      st *= (L.n + 1);
-      f[j] = bit ? xi[j] : T(1) - xi[j];
-      df[j] = bit ? T(1) : T(-1);
-    }
-#pragma unroll
-    for (int gdir = 0; gdir < D; ++gdir) {
-      T dN = 1;
-#pragma unroll
-      for (int j = 0; j < D; ++j) dN *= (j == gdir) ? df[j] : f[j];
-#pragma unroll
-      for (int i = 0; i < D; ++i) J[i][gdir] += (T)verts[vi * D + i] * dN;
-    }
-  }
-  T Ji[D][D], det;
-  if constexpr (D == 2) {
-    det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-    T id = T(1) / det;
-    Ji[0][0] = J[1][1] * id; Ji[0][1] = -J[0][1] * id; Ji[1][0] = -J[1][0] * id; Ji[1][1] = J[0][0] * id;
-  } else {
-    T c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-    T c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-    T c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-    T id = T(1) / det;
-    Ji[0][0] = c00 * id; Ji[1][0] = c01 * id; Ji[2][0] = c02 * id;
-    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
-    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
-    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
-    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
-    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
-    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
-  }
-  T jxw = det;
-#pragma unroll
-  for (int j = 0; j < D; ++j) jxw *= sgw[pq[j]];
-  const T nu = nu_q ? nu_q[cell * NL + p] : nu_const;
+// out = sum_m c[m] v(source lane of permutation m), along x (DIR 0) or y (DIR 1)
+template <int DIR, typename T>
+__device__ __forceinline__ T lane_contract(T v, const T* c) {
+  if constexpr (DIR == 0)
+    return c[0] * v + c[1] * dpp<kQuadRot1>(v) + c[2] * dpp<kQuadRot2>(v) + c[3] * dpp<kQuadRot3>(v);
+  else
+    return c[0] * v + c[1] * dpp<kRowRot1>(v) + c[2] * dpp<kRowRot2>(v) + c[3] * dpp<kRowRot3>(v);
+}
 
-  // ---- values at the quadrature points of all temporal dofs (and of the
-  // last dof of the previous subinterval)
-  int cur = 0;
-  auto pp_interp = [&](T v) -> T {
-#pragma unroll
-    for (int dir = 0; dir < D; ++dir) {
-      T* buf = cur ? bufB : bufA;
-      buf[p] = v;
-      __syncthreads();
-      v = contract<T, Q>(buf, p, dir, sS, false);
-      cur ^= 1;
-    }
-    return v;
-  };
-  T ub[4][D];
-  T up[D];
-#pragma unroll
-  for (int b = 0; b < 4; ++b)
-#pragma unroll
-    for (int comp = 0; comp < D; ++comp) {
-      ub[b][comp] = 0;
-      if (b < nt) {
-        T v = (active && fr) ? x[vidx(L, n, b, comp, g)] : T(0);
-        ub[b][comp] = pp_interp(v);
-      }
-    }
-#pragma unroll
-  for (int comp = 0; comp < D; ++comp) {
-    T v = (active && fr && n > 0) ? x[vidx(L, n - 1, nt - 1, comp, g)] : T(0);
-    up[comp] = (n > 0) ? pp_interp(v) : T(0);
-  }
-  for (int t = p; t < nt * C; t += NL) pv[t] = active ? x[pidx(L, n, t / C, cell, t % C)] : T(0);
-  __syncthreads();
+// Sum over the 16 lanes of a row; every lane receives the sum.
+template <typename T>
+__device__ __forceinline__ T row_sum16(T v) {
+  v += dpp<kRowRot2>(v);
+  v += dpp<kRowRot3>(v);
+  v += dpp<kQuadRot2>(v);
+  v += dpp<kQuadSwap1>(v);
+  return v;
+}
 
+// Offsets passed through an empty asm statement: the compiler may not hoist
+// the small table reads that use them out of the subinterval loop (which
+// would pin dozens of registers for the whole kernel).
+__device__ __forceinline__ int opaque_v(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+__device__ __forceinline__ int opaque_s(int v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
+// Pencil contraction with 1D matrix `mat` (0: S, 1: Dg, 2: S^T, 3: Dg^T) along
+// direction DIR of a cell.  x / y: per-lane coefficients cxy[co + m] in LDS
+// (co = mat * 16 + position * 4); z: the Q x Q matrices in global memory
+// (uniform reads), tS / tDg.
+template <int DIR, int Q, int ZP, typename T>
+__device__ __forceinline__ void pencil(const T (&v)[ZP], T (&o)[ZP], int mat, const T* cxy, int co,
+                                       const T* __restrict__ tz) {
+  if constexpr (DIR == 2) {
+    const T* M = tz + opaque_s((mat & 1) * Q * Q);
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    if (a >= nt) break;
-    const T ca = scoef[a];
-    T pres = 0;
-    for (int l = 0; l < C; ++l) pres += spsi[p * C + l] * pv[a * C + l];
-    T div = 0;
-#pragma unroll
-    for (int comp = 0; comp < D; ++comp) {
-      T W = 0;
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (b < nt) W += sK[a * nt + b] * ub[b][comp];
-      W -= sphi[a] * up[comp];
-      // reference gradient of u_a at the Gauss points (collocation derivative)
-      T gr[D];
-      {
-        T* buf = cur ? bufB : bufA;
-        buf[p] = ub[a][comp];
-        __syncthreads();
-#pragma unroll
-        for (int dir = 0; dir < D; ++dir) gr[dir] = contract<T, Q>(buf, p, dir, sDg, false);
-        cur ^= 1;
-      }
-      // physical gradient J^{-T} gr, flux F = c_a (nu grad u - p e_comp), G = J^{-1} F JxW
-      T gp[D];
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        T s = 0;
-#pragma unroll
-        for (int j = 0; j < D; ++j) s += Ji[j][i] * gr[j];
-        gp[i] = s;
-      }
-      div += gp[comp];
-      T Fl[D];
-#pragma unroll
-      for (int i = 0; i < D; ++i) Fl[i] = ca * nu * gp[i] - (i == comp ? ca * pres : T(0));
-      T Gr[D];
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        T s = 0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) s += Ji[j][i] * Fl[i];
-        Gr[j] = s * jxw;
-      }
-      g0[p] = Gr[0];
-      g1[p] = Gr[1];
-      if constexpr (D == 3) g2[p] = Gr[2];
-      __syncthreads();
-      T Z = W * jxw + contract<T, Q>(g0, p, 0, sDg, true) + contract<T, Q>(g1, p, 1, sDg, true);
-      if constexpr (D == 3) Z += contract<T, Q>(g2, p, 2, sDg, true);
-      // back to the nodes: transposed interpolation
-#pragma unroll
-      for (int dir = 0; dir < D; ++dir) {
-        T* buf = cur ? bufB : bufA;
-        buf[p] = Z;
-        __syncthreads();
-        Z = contract<T, Q>(buf, p, dir, sS, true);
-        cur ^= 1;
-      }
-      if (active)
-        E[cell * (int64_t)D * nt * NL * L.N + ((int64_t)(n * nt + a) * D + comp) * NL + p] = Z;
-    }
-    // continuity: y_p[l] += -c_a sum_q psi_l div JxW
-    g0[p] = -ca * div * jxw;
-    __syncthreads();
-    if (active && p < C) {
+    for (int z = 0; z < ZP; ++z) {
       T s = 0;
-      for (int q = 0; q < NL; ++q) s += spsi[q * C + p] * g0[q];
-      const int64_t id = pidx(L, n, a, cell, p);
-      y[id] = (mode ? b[id] : T(0)) + sgn * s;
+#pragma unroll
+      for (int t = 0; t < ZP; ++t) s += (mat < 2 ? M[z * Q + t] : M[t * Q + z]) * v[t];
+      o[z] = s;
+    }
+  } else {
+    const int c0 = opaque_v(co);
+    T cc[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) cc[m] = cxy[c0 + m];
+#pragma unroll
+    for (int z = 0; z < ZP; ++z) o[z] = lane_contract<DIR>(v[z], cc);
+  }
+}
+
+}  // namespace
+
+template <typename T, int D, int Q, int NT>
+__global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict__ geo, const T* __restrict__ tab,
+                                               const T* __restrict__ x, const T* __restrict__ b,
+                                               T* __restrict__ y, T* __restrict__ E, int mode, int nper) {
+  constexpr int ZP = D == 3 ? Q : 1;
+  constexpr int NL = D == 3 ? Q * Q * Q : Q * Q;
+  constexpr int NG = 1 + D * D + D * (D + 1) / 2;
+  constexpr int NS = D * (D + 1) / 2;
+  constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
+  __shared__ __align__(16) T sCX[64];
+  __shared__ __align__(16) T sCY[64];
+  __shared__ T sPsi[16 * ZP * C];
+  __shared__ int sSrc[2][4][4];
+  const int tid = threadIdx.x, lane16 = tid & 15, qx = lane16 & 3, qy = lane16 >> 2;
+  const T* tS = tab;
+  const T* tDg = tS + Q * Q;
+  const T* tK = tDg + Q * Q + 2 * Q;
+  const T* tphi = tK + NT * NT;
+  const T* tcoef = tphi + NT;
+  const T* tpsi = tcoef + NT;
+
+  // ---- source lanes of the DPP permutations (wave 0, all lanes active)
+  if (tid < 64) {
+    const int sx1 = dpp_i<kQuadRot1>(qx), sx2 = dpp_i<kQuadRot2>(qx), sx3 = dpp_i<kQuadRot3>(qx);
+    const int sy1 = dpp_i<kRowRot1>(lane16) >> 2, sy2 = dpp_i<kRowRot2>(lane16) >> 2,
+              sy3 = dpp_i<kRowRot3>(lane16) >> 2;
+    if (tid < 16 && qy == 0) {
+      sSrc[0][0][qx] = qx; sSrc[0][1][qx] = sx1; sSrc[0][2][qx] = sx2; sSrc[0][3][qx] = sx3;
+    }
+    if (tid < 16 && qx == 0) {
+      sSrc[1][0][qy] = qy; sSrc[1][1][qy] = sy1; sSrc[1][2][qy] = sy2; sSrc[1][3][qy] = sy3;
+    }
+  }
+  __syncthreads();
+  auto mat_el = [&](int mat, int i, int t) -> T {
+    if (i >= Q || t >= Q) return T(0);
+    const T* M = (mat & 1) ? tDg : tS;
+    return mat < 2 ? M[i * Q + t] : M[t * Q + i];
+  };
+  if (tid < 64) {
+    const int mat = tid >> 4, i = (tid >> 2) & 3, m = tid & 3;
+    sCX[tid] = mat_el(mat, i, sSrc[0][m][i]);
+    sCY[tid] = mat_el(mat, i, sSrc[1][m][i]);
+  }
+  for (int t = tid; t < 16 * ZP * C; t += blockDim.x) {
+    const int l = t % C, z = (t / C) % ZP, ll = t / (C * ZP), px = ll & 3, py = ll >> 2;
+    sPsi[t] = (px < Q && py < Q) ? tpsi[(px + Q * py + Q * Q * z) * C + l] : T(0);
+  }
+  __syncthreads();
+
+  // ---- this lane's cell, chunk of subintervals and nodes
+  const int64_t ncells = L.Mp / C;
+  const int64_t nbx = gridDim.x;
+  const int64_t lb = xcd_remap(blockIdx.x + nbx * blockIdx.y, nbx * gridDim.y);
+  const int64_t cid = (lb % nbx) * 16 + (tid >> 4);
+  const int n0 = (int)(lb / nbx) * nper;
+  const int n1 = min(L.N, n0 + nper);
+  const bool cvalid = cid < ncells;
+  const bool lvalid = cvalid && qx < Q && qy < Q;
+  const int64_t cell = cvalid ? cid : 0;
+  const int cc0 = (int)(cell % L.n), cc1 = (int)((cell / L.n) % L.n),
+            cc2 = D == 3 ? (int)(cell / ((int64_t)L.n * L.n)) : 0;
+  const int gxn = cc0 * L.q + qx, gyn = cc1 * L.q + qy;
+  const bool fxy = lvalid && gxn > 0 && gxn < L.nn - 1 && gyn > 0 && gyn < L.nn - 1;
+  int gnd[ZP];  // node index (< 2^31: checked on the host)
+  bool fre[ZP];
+#pragma unroll
+  for (int z = 0; z < ZP; ++z) {
+    const int gzn = cc2 * L.q + z;
+    gnd[z] = gxn + L.nn * (gyn + (D == 3 ? L.nn * gzn : 0));
+    fre[z] = fxy && (D == 2 || (gzn > 0 && gzn < L.nn - 1));
+  }
+  const T* gc = geo + (cell * NG * 16 + lane16) * ZP;  // geo[cell][f][lane16][z]
+  // E: per field (n, a, comp) a grid of (Q n)^d duplicated nodes (each cell
+  // keeps its own copy of shared nodes), x fastest
+  const int W = Q * L.n;
+  const int64_t NE = D == 3 ? (int64_t)W * W * W : (int64_t)W * W;
+  T* Ec = E + (cc0 * Q + qx) + (int64_t)W * (cc1 * Q + qy) + (D == 3 ? (int64_t)W * W * cc2 * Q : 0);
+  const int po = lane16 * ZP * C;  // this lane's psi rows
+
+  // nodal values of (n, temporal dof bb, comp) interpolated to the Gauss points
+  auto interp = [&](int n, int bb, int comp, T (&uq)[ZP]) {
+    T v[ZP], w[ZP];
+    const T* xs = x + (int64_t)n * L.slab + (int64_t)bb * L.Mv + (int64_t)comp * L.nodes;
+#pragma unroll
+    for (int z = 0; z < ZP; ++z) v[z] = fre[z] ? xs[gnd[z]] : T(0);
+    pencil<0, Q, ZP>(v, w, 0, sCX, qx * 4, tS);
+    if constexpr (D == 3) {
+      pencil<1, Q, ZP>(w, v, 0, sCY, qy * 4, tS);
+      pencil<2, Q, ZP>(v, uq, 0, sCX, 0, tS);
+    } else {
+      pencil<1, Q, ZP>(w, uq, 0, sCY, qy * 4, tS);
+    }
+  };
+
+#pragma unroll 1
+  for (int comp = 0; comp < D; ++comp) {
+    // geometry of this component: JxW, nu JxW J^-1 J^-T, column comp of JxW J^-1
+    T jw[ZP], gm[NS][ZP], ja[D][ZP];
+#pragma unroll
+    for (int z = 0; z < ZP; ++z) {
+      jw[z] = gc[z];
+#pragma unroll
+      for (int j = 0; j < D; ++j) ja[j][z] = gc[(1 + j * D + comp) * 16 * ZP + z];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) gm[t][z] = gc[(1 + D * D + t) * 16 * ZP + z];
+    }
+    T up[ZP];
+    if (n0 > 0 && n0 < n1) interp(n0 - 1, NT - 1, comp, up);
+    else
+#pragma unroll
+      for (int z = 0; z < ZP; ++z) up[z] = 0;
+
+    for (int n = n0; n < n1; ++n) {
+      T uq[NT][ZP];
+#pragma unroll
+      for (int bb = 0; bb < NT; ++bb) interp(n, bb, comp, uq[bb]);
+      // temporal dofs one at a time (not unrolled: bounded register use); uq is
+      // rotated so that uq[0] holds dof a and uq[j] holds dof (a + j) mod NT
+#pragma unroll 1
+      for (int a = 0; a < NT; ++a) {
+        const T ca = tcoef[a];
+        // pressure of dof a at the Gauss points
+        T pres[ZP];
+        {
+          const T* ps = x + (int64_t)n * L.slab + (int64_t)NT * L.Mv + (int64_t)a * L.Mp + cell * C +
+                        opaque_v(0);
+          T pl[C];
+#pragma unroll
+          for (int l = 0; l < C; ++l) pl[l] = cvalid ? ps[l] : T(0);
+          const int pr = opaque_v(po);
+#pragma unroll
+          for (int z = 0; z < ZP; ++z) {
+            T s = 0;
+#pragma unroll
+            for (int l = 0; l < C; ++l) s += sPsi[pr + z * C + l] * pl[l];
+            pres[z] = s;
+          }
+        }
+        T Zq[ZP];
+#pragma unroll
+        for (int z = 0; z < ZP; ++z) {
+          T w = -tphi[a] * up[z];
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            const int bb = a + j < NT ? a + j : a + j - NT;
+            w += tK[a * NT + bb] * uq[j][z];
+          }
+          Zq[z] = w * jw[z];
+        }
+        T g[3][ZP];
+        pencil<0, Q, ZP>(uq[0], g[0], 1, sCX, 16 + qx * 4, tS);
+        pencil<1, Q, ZP>(uq[0], g[1], 1, sCY, 16 + qy * 4, tS);
+        if constexpr (D == 3) pencil<2, Q, ZP>(uq[0], g[2], 1, sCX, 0, tS);
+        T dv[ZP];
+#pragma unroll
+        for (int z = 0; z < ZP; ++z) {
+          T gr[D];
+#pragma unroll
+          for (int j = 0; j < D; ++j) gr[j] = g[j][z];
+          T dsum = 0;
+#pragma unroll
+          for (int j = 0; j < D; ++j) {
+            T s = 0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+              const int t = j <= k ? j * D - j * (j - 1) / 2 + (k - j) : k * D - k * (k - 1) / 2 + (j - k);
+              s += gm[t][z] * gr[k];
+            }
+            g[j][z] = ca * (s - pres[z] * ja[j][z]);
+            dsum += ja[j][z] * gr[j];
+          }
+          dv[z] = -ca * dsum;
+        }
+        // test with the reference gradients (transposed collocation derivative)
+        T t1[ZP];
+        pencil<0, Q, ZP>(g[0], t1, 3, sCX, 48 + qx * 4, tS);
+#pragma unroll
+        for (int z = 0; z < ZP; ++z) Zq[z] += t1[z];
+        pencil<1, Q, ZP>(g[1], t1, 3, sCY, 48 + qy * 4, tS);
+#pragma unroll
+        for (int z = 0; z < ZP; ++z) Zq[z] += t1[z];
+        if constexpr (D == 3) {
+          pencil<2, Q, ZP>(g[2], t1, 3, sCX, 0, tS);
+#pragma unroll
+          for (int z = 0; z < ZP; ++z) Zq[z] += t1[z];
+        }
+        // back to the nodes: transposed interpolation
+        pencil<0, Q, ZP>(Zq, t1, 2, sCX, 32 + qx * 4, tS);
+        if constexpr (D == 3) {
+          pencil<1, Q, ZP>(t1, Zq, 2, sCY, 32 + qy * 4, tS);
+          pencil<2, Q, ZP>(Zq, t1, 2, sCX, 0, tS);
+        } else {
+          pencil<1, Q, ZP>(t1, Zq, 2, sCY, 32 + qy * 4, tS);
+#pragma unroll
+          for (int z = 0; z < ZP; ++z) t1[z] = Zq[z];
+        }
+        if (lvalid) {
+          T* Eo = Ec + ((int64_t)(n * NT + a) * D + comp) * NE;
+#pragma unroll
+          for (int z = 0; z < ZP; ++z) Eo[(int64_t)W * W * z] = t1[z];
+        }
+        // continuity rows of dof a: y_p[l] (+)= -c_a sum_q psi_l(q) JxW d_comp u_a(q),
+        // accumulated over the components in a fixed order
+        {
+          const int pr = opaque_v(po);
+          T mine = 0;
+#pragma unroll
+          for (int l = 0; l < C; ++l) {
+            T s = 0;
+#pragma unroll
+            for (int z = 0; z < ZP; ++z) s += sPsi[pr + z * C + l] * dv[z];
+            s = row_sum16(s);
+            if (lane16 == l) mine = s;
+          }
+          if (cvalid && lane16 < C) {
+            const int64_t id = (int64_t)n * L.slab + (int64_t)NT * L.Mv + (int64_t)a * L.Mp + cell * C + lane16;
+            const T prev = comp > 0 ? y[id] : (mode ? b[id] : T(0));
+            y[id] = mode ? prev - mine : prev + mine;
+          }
+        }
+        // rotate: uq[j] <- uq[j + 1]
+#pragma unroll
+        for (int z = 0; z < ZP; ++z) {
+          const T first = uq[0][z];
+#pragma unroll
+          for (int j = 0; j + 1 < NT; ++j) uq[j][z] = uq[j + 1][z];
+          uq[NT - 1][z] = first;
+        }
+      }
+      // after NT rotations uq is back in order; the last dof feeds the next jump term
+#pragma unroll
+      for (int z = 0; z < ZP; ++z) up[z] = uq[NT - 1][z];
     }
   }
 }
 
-// Velocity rows of y = S x (mode 0) / y = b - S x (mode 1): sum the cell
-// contributions of every node in a fixed order; Dirichlet rows are the identity.
-template <typename T, int D>
-__global__ void k_apply_gather(LevelArgs L, const T* __restrict__ E, const T* __restrict__ x,
-                               const T* __restrict__ b, T* __restrict__ y, int mode) {
-  const int64_t per = (int64_t)L.nt * D * L.nodes;
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)L.N * per) return;
-  const int n = (int)(idx / per);
-  int64_t rem = idx % per;
-  const int a = (int)(rem / ((int64_t)D * L.nodes));
-  rem %= (int64_t)D * L.nodes;
-  const int comp = (int)(rem / L.nodes);
-  const int64_t g = rem % L.nodes;
-  const int64_t id = vidx(L, n, a, comp, g);
-  int gj[3] = {(int)(g % L.nn), (int)((g / L.nn) % L.nn), D == 3 ? (int)(g / ((int64_t)L.nn * L.nn)) : 0};
-  int cj[3][2], ij[3][2], nj[3] = {1, 1, 1};
-  bool bnd = false;
-  for (int j = 0; j < D; ++j) {
-    if (gj[j] == 0 || gj[j] == L.nn - 1) bnd = true;
-    int c = gj[j] / L.q, i = gj[j] % L.q;
-    if (c == L.n) { c = L.n - 1; i = L.q; }
-    if (i == 0 && c > 0) {
-      cj[j][0] = c - 1; ij[j][0] = L.q;
-      cj[j][1] = c;     ij[j][1] = 0;
-      nj[j] = 2;
-    } else {
-      cj[j][0] = c; ij[j][0] = i;
+// Node gathers over the duplicated-grid scratch E.  One thread owns the q
+// nodes g = q c + j (j < q) of cell interval c along x in one row (y, z) of one
+// field; the thread of the last interval also owns the last node of the row.
+// Node g has duplicated index Q c + j in its own cell and, for j = 0 and c > 0,
+// Q c - 1 in the cell below; the same holds along y and z (row-uniform).
+// Launch: 256 threads = XW intervals x (256 / XW) rows (XW = 2^lxw, the
+// smallest power of two >= n, at most 64), grid (ceil(n / XW),
+// ceil(nn / rows) nn (3D) or ceil(nn / rows) (2D), d nt N fields).
+//   KIND 0 (operator): y = sum (mode 0) or b - sum (mode 1); Dirichlet rows identity
+//   KIND 1 (smoother): x += omega / valence * sum; Dirichlet nodes unchanged
+template <typename T, int D, int QQ, int KIND>
+__global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __restrict__ E, const T* __restrict__ xin,
+                                                     const T* __restrict__ b, T* __restrict__ out, int mode,
+                                                     T omega, int lxw) {
+  constexpr int q = QQ - 1;
+  const int c = (blockIdx.x << lxw) + (int)(threadIdx.x & ((1 << lxw) - 1));
+  const int rows = 256 >> lxw, nyb = (L.nn + rows - 1) / rows;
+  const int by = blockIdx.y;
+  const int gy = (D == 3 ? by % nyb : by) * rows + (int)(threadIdx.x >> lxw);
+  const int gz = D == 3 ? by / nyb : 0;
+  if (c >= L.n || gy >= L.nn) return;
+  const int64_t field = blockIdx.z;  // (n nt + a) D + comp
+  const int comp = (int)(field % D);
+  const int64_t fa = field / D;
+  const int64_t row0 = (fa / L.nt) * L.slab + (fa % L.nt) * L.Mv + (int64_t)comp * L.nodes +
+                       (int64_t)L.nn * (gy + (int64_t)L.nn * gz);
+  const bool brow = gy == 0 || gy == L.nn - 1 || (D == 3 && (gz == 0 || gz == L.nn - 1));
+  const int g0 = q * c;
+  const bool last = c == L.n - 1;
+  if (brow) {  // every node of a boundary row is a Dirichlet node
+    if (KIND == 0) {
+#pragma unroll
+      for (int j = 0; j < q + 1; ++j) {
+        if (j == q && !last) break;
+        const int64_t id = row0 + g0 + j;
+        out[id] = mode ? b[id] - xin[id] : xin[id];
+      }
     }
-  }
-  if (bnd) {
-    y[id] = mode ? b[id] - x[id] : x[id];
     return;
   }
-  const int64_t stride = (int64_t)D * L.nt * L.nloc * L.N;
-  const int64_t off = ((int64_t)(n * L.nt + a) * D + comp) * L.nloc;
-  T s = 0;
-  for (int u = 0; u < (D == 3 ? nj[2] : 1); ++u)
-    for (int v = 0; v < nj[1]; ++v)
-      for (int w = 0; w < nj[0]; ++w) {
-        int64_t cell = cj[0][w] + (int64_t)L.n * (cj[1][v] + (int64_t)L.n * (D == 3 ? cj[2][u] : 0));
-        int i = ij[0][w] + L.Q * (ij[1][v] + L.Q * (D == 3 ? ij[2][u] : 0));
-        s += E[cell * stride + off + i];
+  const int W = QQ * L.n;
+  const int64_t NE = D == 3 ? (int64_t)W * W * W : (int64_t)W * W;
+  const T* Ef = E + field * NE;
+  const int ny = (gy % q == 0) ? 2 : 1, nz = D == 3 ? ((gz % q == 0) ? 2 : 1) : 1;
+  const int dy = gy + gy / q, dz = gz + gz / q;
+  T own[q], below = T(0);
+#pragma unroll
+  for (int j = 0; j < q; ++j) own[j] = T(0);
+  // fixed order (u, v), own cell then the cell below along x
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    if (u >= nz) break;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      if (v >= ny) break;
+      const T* er = Ef + (D == 3 ? (int64_t)(dz - u) * W * W : 0) + (int64_t)(dy - v) * W + (int64_t)QQ * c;
+      T ev[q];
+      if constexpr (QQ == 4 && sizeof(T) == 4) {  // 16-byte aligned
+        const float4 t4 = *reinterpret_cast<const float4*>(er);
+        ev[0] = t4.x; ev[1] = t4.y; ev[2] = t4.z;
+      } else if constexpr (QQ == 4) {
+        const double2 t0 = *reinterpret_cast<const double2*>(er);
+        ev[0] = t0.x; ev[1] = t0.y; ev[2] = er[2];
+      } else {
+#pragma unroll
+        for (int j = 0; j < q; ++j) ev[j] = er[j];
       }
-  y[id] = mode ? b[id] - s : s;
+#pragma unroll
+      for (int j = 0; j < q; ++j) own[j] += ev[j];
+      if (c > 0) below += er[-1];
+    }
+  }
+  const T vyz = T(ny * nz);
+#pragma unroll
+  for (int j = 0; j < q + 1; ++j) {
+    if (j == q && !last) break;
+    const int g = g0 + j;
+    const int64_t id = row0 + g;
+    const bool dir = g == 0 || g == L.nn - 1;
+    const T sj = j < q ? (j == 0 && c > 0 ? own[0] + below : own[j < q ? j : 0]) : T(0);
+    if (KIND == 0) {
+      if (dir) out[id] = mode ? b[id] - xin[id] : xin[id];
+      else out[id] = mode ? b[id] - sj : sj;
+    } else if (!dir) {
+      const T val = (j == 0 && c > 0) ? vyz * T(2) : vyz;
+      out[id] += omega / val * sj;
+    }
+  }
 }
 
-template <typename T, int D, int Q>
-static hipError_t apply_impl(const LevelArgs& L, const double* verts, const T* nu_q, T nu_const, const T* tab,
-                             const T* x, const T* b, T* y, int mode, T* E, hipStream_t s) {
-  constexpr int NL = D == 2 ? Q * Q : Q * Q * Q;
-  constexpr int CPB = 64 / NL;
-  const int tabn = table_size(Q, L.nt, NL, L.C);
-  size_t shm = sizeof(T) * (((tabn + 1) & ~1) + (CPB + 1) * (5 * NL + L.nt * L.C));
-  int64_t ncells = L.Mp / L.C;
-  dim3 grid((unsigned)((ncells + CPB - 1) / CPB), (unsigned)L.N);
-  k_apply<T, D, Q><<<grid, 64, shm, s>>>(L, verts, nu_q, nu_const, tab, x, b, y, E, mode);
-  int64_t nv = (int64_t)L.N * L.nt * D * L.nodes;
-  k_apply_gather<T, D><<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(L, E, x, b, y, mode);
-  return hipGetLastError();
+static int gather_lxw(const LevelArgs& L) {
+  int l = 0;
+  while ((1 << l) < L.n && l < 6) ++l;
+  return l;
+}
+template <int D>
+static dim3 gather_grid(const LevelArgs& L, int lxw) {
+  const int rows = 256 >> lxw;
+  const int64_t nyb = (L.nn + rows - 1) / rows, gy = D == 3 ? nyb * L.nn : nyb, gz = (int64_t)L.N * L.nt * D;
+  if (gy > 65535 || gz > 65535) return dim3(0, 0, 0);  // launch fails: invalid configuration
+  return dim3((unsigned)((L.n + (1 << lxw) - 1) >> lxw), (unsigned)gy, (unsigned)gz);
+}
+
+template <typename T, int KIND>
+static hipError_t node_gather(const LevelArgs& L, const T* E, const T* xin, const T* b, T* out, int mode, T omega,
+                              hipStream_t s) {
+#define STMG_NG(DD, QQ)                                                                                  \
+  if (L.d == DD && L.Q == QQ) {                                                                           \
+    const int lxw = gather_lxw(L);                                                                      \
+    k_node_gather<T, DD, QQ, KIND><<<gather_grid<DD>(L, lxw), 256, 0, s>>>(L, E, xin, b, out, mode, omega, lxw); \
+    return hipGetLastError();                                                                             \
+  }
+  STMG_NG(2, 3) STMG_NG(2, 4) STMG_NG(3, 3) STMG_NG(3, 4)
+#undef STMG_NG
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int D, int Q, int NT>
+static hipError_t apply_impl(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y,
+                             int mode, T* E, hipStream_t s) {
+  constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
+  if (L.C != C || L.nt != NT || L.Q != Q || L.nodes >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  const int64_t ncells = L.Mp / L.C;
+  const int64_t nbx = (ncells + 15) / 16;
+  // split the subintervals into chunks when there are too few cells to fill the chip
+  int64_t nchunk = std::min<int64_t>(L.N, std::max<int64_t>(1, (4096 + 4 * nbx - 1) / (4 * nbx)));
+  const int nper = (int)((L.N + nchunk - 1) / nchunk);
+  nchunk = (L.N + nper - 1) / nper;
+  k_apply<T, D, Q, NT><<<dim3((unsigned)nbx, (unsigned)nchunk), 256, 0, s>>>(L, geo, tab, x, b, y,
+                                                                                             E, mode, nper);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return node_gather<T, 0>(L, E, x, b, y, mode, T(0), s);
 }
 
 template <typename T>
-hipError_t launch_apply(const LevelArgs& L, const double* verts, const T* nu_q, T nu_const, const T* tab,
-                        const T* x, const T* b, T* y, int mode, T* E, hipStream_t s) {
-  if (L.d == 2 && L.Q == 3) return apply_impl<T, 2, 3>(L, verts, nu_q, nu_const, tab, x, b, y, mode, E, s);
-  if (L.d == 2 && L.Q == 4) return apply_impl<T, 2, 4>(L, verts, nu_q, nu_const, tab, x, b, y, mode, E, s);
-  if (L.d == 3 && L.Q == 3) return apply_impl<T, 3, 3>(L, verts, nu_q, nu_const, tab, x, b, y, mode, E, s);
-  if (L.d == 3 && L.Q == 4) return apply_impl<T, 3, 4>(L, verts, nu_q, nu_const, tab, x, b, y, mode, E, s);
+hipError_t launch_apply(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y, int mode,
+                        T* E, hipStream_t s) {
+#define STMG_AP(DD, QQ, NN) \
+  if (L.d == DD && L.Q == QQ && L.nt == NN) return apply_impl<T, DD, QQ, NN>(L, geo, tab, x, b, y, mode, E, s);
+  STMG_AP(2, 3, 1) STMG_AP(2, 3, 2) STMG_AP(2, 3, 3) STMG_AP(2, 3, 4)
+  STMG_AP(2, 4, 1) STMG_AP(2, 4, 2) STMG_AP(2, 4, 3) STMG_AP(2, 4, 4)
+  STMG_AP(3, 3, 1) STMG_AP(3, 3, 2) STMG_AP(3, 3, 3) STMG_AP(3, 3, 4)
+  STMG_AP(3, 4, 1) STMG_AP(3, 4, 2) STMG_AP(3, 4, 3) STMG_AP(3, 4, 4)
+#undef STMG_AP
   return hipErrorInvalidValue;
 }
 
@@ -391,198 +585,244 @@ struct mfma_vec<double> {
   static __device__ __forceinline__ int row(int lane, int v) { return lane / 16 + 4 * v; }
 };
 
-template <typename T, int D, int N>
+template <typename T, int D, int Q, int NT, int NCT>
 __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __restrict__ Asw,
                                                     const T* __restrict__ Bm, const T* __restrict__ F,
                                                     const T* __restrict__ Hinv, const T* __restrict__ coef,
                                                     const T* __restrict__ r, T* __restrict__ x, T omega,
                                                     T* __restrict__ E) {
-  constexpr int DN = D * N;
-  constexpr int NCT = (DN + 15) / 16;  // column tiles of 16
+  constexpr int NL = D == 3 ? Q * Q * Q : Q * Q;
+  constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
+  constexpr int M = NT * NL, MP = (M + 15) / 16 * 16, NKB = MP / 16, P = NT * C;
   constexpr int DNP = NCT * 16;
+  constexpr int TPW = (NKB + 3) / 4;  // row tiles per wave (4 waves)
+  // double-buffer the A_s^{-1} fragments of the next row tile when registers allow
+  constexpr bool DB = TPW > 1 && NKB * 4 * (int)sizeof(T) <= 192;
   typedef typename mfma_vec<T>::v4 v4;
-  const int nl = L.nloc, nt = L.nt, C = L.C, m = nt * nl, P = nt * C;
-  const int mp = (m + 15) & ~15, nkb = mp / 16;
+  const int N = L.N, lgN = N == 1 ? 0 : (N == 2 ? 1 : (N == 4 ? 2 : 3)), DN = D * N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* RZ = reinterpret_cast<T*>(smem_raw);  // R (B-operand order), then Z (row-major mp x DNP)
-  T* Rp = RZ + (size_t)mp * DNP;
-  T* S = Rp + P * N;
-  T* YP = S + P * N;
-  T* sc = YP + P * N;
-  const int64_t cell = blockIdx.x;
-  int cc[3] = {(int)(cell % L.n), (int)((cell / L.n) % L.n), (int)(cell / ((int64_t)L.n * L.n))};
-  const int tid = threadIdx.x;
-  // ---- gather r into B-operand order; padded rows/columns are zero
-  for (int t = tid; t < mp * DNP; t += blockDim.x) RZ[t] = 0;
-  __syncthreads();
-  for (int t = tid; t < m * DN; t += blockDim.x) {
-    int i = t % nl, rest = t / nl;
-    int a = rest % nt;
-    rest /= nt;
-    int comp = rest % D, n = rest / D;
-    bool fr;
-    int val;
-    int64_t g = gnode<D>(L, cc, i, fr, val);
-    int K = a * nl + i, col = comp * N + n;
-    int ct = col / 16, jj = col % 16, kb = K / 16, rem = K % 16;
-    RZ[(((size_t)ct * nkb + kb) * 64 + jj + 16 * (rem / 4)) * 4 + (rem % 4)] = fr ? r[vidx(L, n, a, comp, g)] : T(0);
+  T* RZ = reinterpret_cast<T*>(smem_raw);  // R (B-operand order), then Z (row-major MP x DNP)
+  T* sB = RZ + MP * DNP;                   // B of this cell, [l][comp][i]
+  T* Rp = sB + C * D * NL;                 // pressure residual [q][n]
+  T* S = Rp + P * 8;
+  T* YP = S + P * 8;
+  T* sc = YP + P * 8;
+  const int64_t cell = xcd_remap(blockIdx.x, gridDim.x);
+  const int cc[3] = {(int)(cell % L.n), (int)((cell / L.n) % L.n), D == 3 ? (int)(cell / ((int64_t)L.n * L.n)) : 0};
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+
+  // ---- A_s^{-1} fragments of this wave's first row tile: issued first, so
+  // that their latency overlaps the residual gather
+  const T* A = Asw + cell * (int64_t)MP * MP;
+  T fa[2][NKB][4];
+  auto load_tile = [&](int t, T (&f)[NKB][4]) {
+    const T* At = A + (int64_t)t * NKB * 256 + lane * 4;
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) f[kb][j] = At[kb * 256 + j];
+  };
+  if (wave < NKB) load_tile(wave, fa[0]);
+
+  // ---- R in B-operand order (padded rows / columns zero), B and the
+  // pressure residual: all loads of this phase are issued before any LDS store
+  {
+    constexpr int PER = MP * DNP / 256;  // entries of R per thread
+    constexpr int PB = (C * D * NL + 255) / 256;
+    const T* Bc = Bm + cell * (int64_t)C * D * NL;
+    T rv[PER], bv[PB];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = tid + 256 * e;  // position in RZ
+      const int r4 = idx & 3, u = idx >> 2, l64 = u & 63;
+      const int K = ((u >> 6) % NKB) * 16 + 4 * (l64 >> 4) + r4;
+      const int col = (u >> 6) / NKB * 16 + (l64 & 15);
+      rv[e] = T(0);
+      if (K < M && col < DN) {
+        const int a = K / NL, i = K % NL;
+        const int comp = col >> lgN, n = col & (N - 1);
+        const int ij[3] = {i % Q, (i / Q) % Q, i / (Q * Q)};
+        bool fr = true;
+        int64_t g = 0, st = 1;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          const int gj = cc[j] * (Q - 1) + ij[j];
+          if (gj == 0 || gj == L.nn - 1) fr = false;
+          g += gj * st;
+          st *= L.nn;
+        }
+        if (fr) rv[e] = r[vidx(L, n, a, comp, g)];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < PB; ++e) {
+      const int t = tid + 256 * e;
+      bv[e] = t < C * D * NL ? Bc[t] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) RZ[tid + 256 * e] = rv[e];
+#pragma unroll
+    for (int e = 0; e < PB; ++e)
+      if (tid + 256 * e < C * D * NL) sB[tid + 256 * e] = bv[e];
   }
-  for (int t = tid; t < P * N; t += blockDim.x) {
-    int q = t % P, n = t / P;
+  if (tid < NT) sc[tid] = coef[tid];
+  for (int t = tid; t < P * N; t += 256) {
+    const int q = t >> lgN, n = t & (N - 1);
     Rp[q * N + n] = r[pidx(L, n, q / C, cell, q % C)];
   }
-  if (tid < nt) sc[tid] = coef[tid];
   __syncthreads();
-  // ---- Z = A_s^{-1} R on the matrix cores
-  const int wave = tid / 64, lane = tid % 64;
-  const int nwave = blockDim.x / 64;
-  const T* A = Asw + (size_t)cell * mp * mp;
-  v4 acc[4][NCT];  // up to 4 row tiles per wave (mp <= 256)
+
+  // ---- Z = A_s^{-1} R on the matrix cores, one 16-row tile at a time
+  v4 acc[TPW][NCT];
 #pragma unroll
-  for (int it = 0; it < 4; ++it) {
-    const int t = wave + it * nwave;
-    if (t < nkb) {
+  for (int it = 0; it < TPW; ++it) {
+    const int t = wave + it * 4;
+    T (&cur)[NKB][4] = fa[DB ? (it & 1) : 0];
+    if (t < NKB) {
+      if (!DB && it > 0) load_tile(t, cur);
+      if (DB && it + 1 < TPW && t + 4 < NKB) load_tile(t + 4, fa[(it + 1) & 1]);
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) acc[it][ct] = v4{0, 0, 0, 0};
-      const T* At = A + (size_t)t * nkb * 256;
-      for (int kb = 0; kb < nkb; ++kb) {
-        const T* ap = At + ((size_t)kb * 64 + lane) * 4;
-        T a0 = ap[0], a1 = ap[1], a2 = ap[2], a3 = ap[3];
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb)
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) {
-          const T* bp = RZ + (((size_t)ct * nkb + kb) * 64 + lane) * 4;
-          acc[it][ct] = mfma_vec<T>::mma(a0, bp[0], acc[it][ct]);
-          acc[it][ct] = mfma_vec<T>::mma(a1, bp[1], acc[it][ct]);
-          acc[it][ct] = mfma_vec<T>::mma(a2, bp[2], acc[it][ct]);
-          acc[it][ct] = mfma_vec<T>::mma(a3, bp[3], acc[it][ct]);
+          const T* bp = RZ + ((ct * NKB + kb) * 64 + lane) * 4;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[it][ct] = mfma_vec<T>::mma(cur[kb][j], bp[j], acc[it][ct]);
         }
-      }
     }
   }
   __syncthreads();  // every wave is done reading R
 #pragma unroll
-  for (int it = 0; it < 4; ++it) {
-    const int t = wave + it * nwave;
-    if (t < nkb)
+  for (int it = 0; it < TPW; ++it) {
+    const int t = wave + it * 4;
+    if (t < NKB)
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          RZ[(size_t)(t * 16 + mfma_vec<T>::row(lane, v)) * DNP + ct * 16 + lane % 16] = acc[it][ct][v];
+          RZ[(t * 16 + mfma_vec<T>::row(lane, v)) * DNP + ct * 16 + lane % 16] = acc[it][ct][v];
+  }
+  // F rows and H^{-1} columns of this thread, issued now (the A fragments are
+  // dead) so that their latency overlaps the Schur complement
+  constexpr int RPT = (D * M + 255) / 256;  // velocity rows per thread
+  constexpr int HPT = (P * 8 + 255) / 256;  // (pp, n) items per thread, N <= 8
+  const T* Fc = F + cell * (int64_t)D * M * P;
+  const T* H = Hinv + cell * (int64_t)P * P;
+  T fv[RPT][P], hv[HPT][P];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int row2 = tid + 256 * j;
+#pragma unroll
+    for (int q = 0; q < P; ++q) fv[j][q] = row2 < D * M ? Fc[((row2 / M) * P + q) * M + row2 % M] : T(0);
+  }
+#pragma unroll
+  for (int j = 0; j < HPT; ++j) {
+    const int t = tid + 256 * j, pp = t >> lgN;
+#pragma unroll
+    for (int q = 0; q < P; ++q) hv[j][q] = t < P * N ? H[q * P + pp] : T(0);
   }
   __syncthreads();
-  T* Z = RZ;
-  // ---- pressure Schur complement
-  const T* B = Bm + cell * (int64_t)C * D * nl;
-  for (int t = tid; t < P * N; t += blockDim.x) {
-    int q = t / N, n = t % N, a = q / C, l = q % C;
+  const T* Z = RZ;
+
+  // ---- pressure Schur complement: S = -c_a B Z - r_p, y_p = H^{-1} S
+  for (int t = tid; t < P * N; t += 256) {
+    const int q = t >> lgN, n = t & (N - 1), a = q / C, l = q % C;
     T s = 0;
+#pragma unroll
     for (int comp = 0; comp < D; ++comp)
-      for (int i = 0; i < nl; ++i) s += B[(l * D + comp) * nl + i] * Z[(size_t)(a * nl + i) * DNP + comp * N + n];
+#pragma unroll 16
+      for (int i = 0; i < NL; ++i) s += sB[(l * D + comp) * NL + i] * Z[(a * NL + i) * DNP + comp * N + n];
     S[q * N + n] = -sc[a] * s - Rp[q * N + n];
   }
   __syncthreads();
-  const T* H = Hinv + cell * (int64_t)P * P;
-  for (int t = tid; t < P * N; t += blockDim.x) {
-    int pp = t / N, n = t % N;
-    T s = 0;
-    for (int q = 0; q < P; ++q) s += H[q * P + pp] * S[q * N + n];
-    YP[pp * N + n] = s;
-    x[pidx(L, n, pp / C, cell, pp % C)] += omega * s;
+#pragma unroll
+  for (int j = 0; j < HPT; ++j) {
+    const int t = tid + 256 * j;
+    if (t < P * N) {
+      const int pp = t >> lgN, n = t & (N - 1);
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < P; ++q) s += hv[j][q] * S[q * N + n];
+      YP[pp * N + n] = s;
+      x[pidx(L, n, pp / C, cell, pp % C)] += omega * s;
+    }
   }
   __syncthreads();
-  // ---- velocity: y = z - F y_p into the cell-local buffer, layout
-  // E[cell][(n nt + a) D + comp][i]
-  const T* Fc = F + cell * (int64_t)D * m * P;
-  T* Ec = E + cell * (int64_t)D * m * N;
-  for (int row2 = tid; row2 < D * m; row2 += blockDim.x) {
-    int comp = row2 / m, row = row2 % m, a = row / nl, i = row % nl;
-    T acc2[N];
+
+  // ---- velocity: y = z - F y_p into the cell-local scratch E
+  const int W = Q * L.n;
+  const int64_t NE = D == 3 ? (int64_t)W * W * W : (int64_t)W * W;
 #pragma unroll
-    for (int n = 0; n < N; ++n) acc2[n] = Z[(size_t)row * DNP + comp * N + n];
-    for (int q = 0; q < P; ++q) {
-      T f = Fc[((int64_t)comp * P + q) * m + row];
+  for (int j = 0; j < RPT; ++j) {
+    const int row2 = tid + 256 * j;
+    if (row2 >= D * M) break;
+    const int comp = row2 / M, row = row2 % M, a = row / NL, i = row % NL;
+    const T(&f)[P] = fv[j];
+    const int64_t eo = (cc[0] * Q + i % Q) + (int64_t)W * ((cc[1] * Q + (i / Q) % Q) +
+                                                           (D == 3 ? (int64_t)W * (cc[2] * Q + i / (Q * Q)) : 0));
 #pragma unroll
-      for (int n = 0; n < N; ++n) acc2[n] -= f * YP[q * N + n];
+    for (int n = 0; n < 8; ++n) {
+      if (n >= N) break;
+      T v = Z[row * DNP + comp * N + n];
+#pragma unroll
+      for (int q = 0; q < P; ++q) v -= f[q] * YP[q * N + n];
+      E[((int64_t)(n * NT + a) * D + comp) * NE + eo] = v;
     }
-#pragma unroll
-    for (int n = 0; n < N; ++n) Ec[((int64_t)(n * nt + a) * D + comp) * nl + i] = acc2[n];
   }
 }
 
-// x_v += omega / valence * (sum over the cells containing the node of E),
-// cells taken in a fixed order (deterministic); Dirichlet nodes unchanged.
-template <typename T, int D>
-__global__ void k_vanka_gather(LevelArgs L, const T* __restrict__ E, T* __restrict__ x, T omega) {
-  const int64_t per = (int64_t)L.nt * D * L.nodes;  // velocity dofs of one subinterval
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)L.N * per) return;
-  const int n = (int)(idx / per);
-  int64_t rem = idx % per;
-  const int a = (int)(rem / ((int64_t)D * L.nodes));
-  rem %= (int64_t)D * L.nodes;
-  const int comp = (int)(rem / L.nodes);
-  const int64_t g = rem % L.nodes;
-  int gj[3] = {(int)(g % L.nn), (int)((g / L.nn) % L.nn), D == 3 ? (int)(g / ((int64_t)L.nn * L.nn)) : 0};
-  // cells containing the node along each direction: (cell, local index)
-  int cj[3][2], ij[3][2], nj[3];
-  for (int j = 0; j < D; ++j) {
-    if (gj[j] == 0 || gj[j] == L.nn - 1) return;  // Dirichlet
-    int c = gj[j] / L.q, i = gj[j] % L.q;
-    if (i == 0) {
-      cj[j][0] = c - 1; ij[j][0] = L.q;
-      cj[j][1] = c;     ij[j][1] = 0;
-      nj[j] = 2;
-    } else {
-      cj[j][0] = c; ij[j][0] = i;
-      nj[j] = 1;
-    }
-  }
-  const int64_t stride = (int64_t)D * L.nt * L.nloc * L.N;  // per cell
-  const int64_t off = ((int64_t)(n * L.nt + a) * D + comp) * L.nloc;
-  T s = 0;
-  int val = 1;
-  for (int j = 0; j < D; ++j) val *= nj[j];
-  for (int u = 0; u < (D == 3 ? nj[2] : 1); ++u)
-    for (int v = 0; v < nj[1]; ++v)
-      for (int w = 0; w < nj[0]; ++w) {
-        int64_t cell = cj[0][w] + (int64_t)L.n * (cj[1][v] + (int64_t)L.n * (D == 3 ? cj[2][u] : 0));
-        int i = ij[0][w] + L.Q * (ij[1][v] + L.Q * (D == 3 ? ij[2][u] : 0));
-        s += E[cell * stride + off + i];
-      }
-  x[vidx(L, n, a, comp, g)] += omega / T(val) * s;
+template <typename T>
+static hipError_t vanka_gather(const LevelArgs& L, const T* E, T* x, T omega, hipStream_t s) {
+  return node_gather<T, 1>(L, E, nullptr, nullptr, x, 0, omega, s);
 }
 
-template <typename T, int D, int N>
+template <typename T, int D, int Q, int NT>
 static hipError_t vanka_fact_impl(const LevelArgs& L, const T* Asw, const T* Bm, const T* F, const T* Hinv,
                                   const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s) {
-  const int m = L.nt * L.nloc, P = L.nt * L.C, mp = (m + 15) & ~15;
-  constexpr int DNP = ((D * N + 15) / 16) * 16;
-  if (mp / 16 > 16) return hipErrorInvalidValue;  // at most 4 row tiles per wave
-  size_t shm = sizeof(T) * ((size_t)mp * DNP + 3 * (size_t)P * N + L.nt + 2);
-  if (shm > 160 * 1024) return hipErrorInvalidValue;
-  int64_t ncells = L.Mp / L.C;
-  k_vanka_mfma<T, D, N><<<(unsigned)ncells, 256, shm, s>>>(L, Asw, Bm, F, Hinv, coef, r, x, omega, E);
-  int64_t nv = (int64_t)L.N * L.nt * D * L.nodes;
-  k_vanka_gather<T, D><<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(L, E, x, omega);
-  return hipGetLastError();
+  constexpr int NL = D == 3 ? Q * Q * Q : Q * Q;
+  constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
+  constexpr int M = NT * NL, MP = (M + 15) / 16 * 16, P = NT * C;
+  if (L.C != C || L.nloc != NL || L.nt != NT || L.N < 1 || L.N > 8 || (L.N & (L.N - 1))) return hipErrorInvalidValue;
+  if (MP / 16 > 16) return hipErrorInvalidValue;  // at most 4 row tiles per wave
+  const int64_t ncells = L.Mp / L.C;
+  const int DN = D * L.N;
+  auto shm = [&](int dnp) { return sizeof(T) * ((size_t)MP * dnp + (size_t)C * D * NL + 3 * (size_t)P * 8 + 8); };
+  auto run = [&](auto kern, size_t bytes) -> hipError_t {
+    if (bytes > 65536) {  // beyond the default dynamic LDS limit
+      hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      if (e != hipSuccess) return e;
+    }
+    kern<<<(unsigned)ncells, 256, bytes, s>>>(L, Asw, Bm, F, Hinv, coef, r, x, omega, E);
+    return hipSuccess;
+  };
+  hipError_t e;
+  if (DN <= 16) {
+    e = run(k_vanka_mfma<T, D, Q, NT, 1>, shm(16));
+  } else if (DN <= 32) {
+    e = run(k_vanka_mfma<T, D, Q, NT, 2>, shm(32));
+  } else {
+    return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  return vanka_gather<T>(L, E, x, omega, s);
 }
 
 template <typename T>
 hipError_t launch_vanka_gather_only(const LevelArgs& L, const T* E, T* x, T omega, hipStream_t s) {
-  int64_t nv = (int64_t)L.N * L.nt * L.d * L.nodes;
-  if (L.d == 3) k_vanka_gather<T, 3><<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(L, E, x, omega);
-  else k_vanka_gather<T, 2><<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(L, E, x, omega);
-  return hipGetLastError();
+  return vanka_gather<T>(L, E, x, omega, s);
 }
 
 template <typename T>
 hipError_t launch_vanka_factored(const LevelArgs& L, const T* Asw, const T* Bm, const T* F, const T* Hinv,
                                  const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s) {
-#define STMG_VF(DD, NN) \
-  if (L.d == DD && L.N == NN) return vanka_fact_impl<T, DD, NN>(L, Asw, Bm, F, Hinv, coef, r, x, omega, E, s);
-  STMG_VF(2, 1) STMG_VF(2, 2) STMG_VF(2, 4) STMG_VF(2, 8)
-  STMG_VF(3, 1) STMG_VF(3, 2) STMG_VF(3, 4) STMG_VF(3, 8)
+#define STMG_VF(DD, QQ, KK) \
+  if (L.d == DD && L.Q == QQ && L.nt == KK) return vanka_fact_impl<T, DD, QQ, KK>(L, Asw, Bm, F, Hinv, coef, r, x, omega, E, s);
+  STMG_VF(2, 3, 1) STMG_VF(2, 3, 2) STMG_VF(2, 3, 3) STMG_VF(2, 3, 4)
+  STMG_VF(2, 4, 1) STMG_VF(2, 4, 2) STMG_VF(2, 4, 3) STMG_VF(2, 4, 4)
+  STMG_VF(3, 3, 1) STMG_VF(3, 3, 2) STMG_VF(3, 3, 3) STMG_VF(3, 3, 4)
+  STMG_VF(3, 4, 1) STMG_VF(3, 4, 2) STMG_VF(3, 4, 3) STMG_VF(3, 4, 4)
 #undef STMG_VF
   return hipErrorInvalidValue;
 }
@@ -686,32 +926,34 @@ struct ArrLayout {  // where array b of a batch of d-dimensional node arrays liv
   int nt, D;
   int64_t slab, Mv, nodes, compact_stride;
 };
-__device__ __forceinline__ int64_t arr_base(const ArrLayout& A, int64_t b) {
-  if (!A.level) return b * A.compact_stride;
-  int comp = (int)(b % A.D);
-  int64_t t = b / A.D;
-  int a = (int)(t % A.nt);
-  int64_t n = t / A.nt;
-  return n * A.slab + (int64_t)a * A.Mv + (int64_t)comp * A.nodes;
+__device__ __forceinline__ int64_t arr_base(const ArrLayout& A, int64_t b64) {
+  if (!A.level) return b64 * A.compact_stride;
+  const unsigned b = (unsigned)b64;  // array counts stay below 2^32
+  const unsigned comp = b % (unsigned)A.D, t = b / (unsigned)A.D;
+  const unsigned a = t % (unsigned)A.nt, n = t / (unsigned)A.nt;
+  return (int64_t)n * A.slab + (int64_t)a * A.Mv + (int64_t)comp * A.nodes;
 }
 
 // out[b][..o..] (+)= sum_t M[o][t] in[b][..t..] along `axis`;
-// dims_out[3] (x, y, z), nin = extent of the input along the axis.
+// dims_out (dx, dy, dz), nin = extent of the input along the axis.  Launch:
+// 64 x 4 threads per block, grid (ceil(dx/64), ceil(dy/4) dz, nb).
 template <typename T>
-__global__ void k_vpass(const T* __restrict__ in, ArrLayout li, T* __restrict__ out, ArrLayout lo, int64_t nb,
-                        int d, int axis, int dx, int dy, int dz, int nin, const T* __restrict__ M,
-                        const int* __restrict__ lo_, const int* __restrict__ hi_, int mask_in, int mask_out,
-                        int accumulate) {
-  const int64_t per = (int64_t)dx * dy * dz;
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nb * per) return;
-  int64_t b = idx / per, e = idx % per;
-  int o[3] = {(int)(e % dx), (int)((e / dx) % dy), (int)(e / ((int64_t)dx * dy))};
-  int dims_out[3] = {dx, dy, dz};
+__global__ __launch_bounds__(256) void k_vpass(const T* __restrict__ in, ArrLayout li, T* __restrict__ out,
+                                               ArrLayout lo, int d, int axis, int dx, int dy, int dz, int nin,
+                                               const T* __restrict__ M, const int* __restrict__ lo_,
+                                               const int* __restrict__ hi_, int mask_in, int mask_out,
+                                               int accumulate) {
+  const int bx = blockIdx.x, by = blockIdx.y;
+  const int64_t b = blockIdx.z;
+  const int ny4 = (dy + 3) / 4;
+  const int o[3] = {bx * 64 + (int)(threadIdx.x & 63), (by % ny4) * 4 + (int)(threadIdx.x >> 6), by / ny4};
+  if (o[0] >= dx || o[1] >= dy) return;
+  const int64_t e = o[0] + (int64_t)dx * (o[1] + (int64_t)dy * o[2]);
+  const int dims_out[3] = {dx, dy, dz};
   int dims_in[3] = {dx, dy, dz};
   dims_in[axis] = nin;
   const T* src = in + arr_base(li, b);
-  int64_t strides[3] = {1, dims_in[0], (int64_t)dims_in[0] * dims_in[1]};
+  const int64_t strides[3] = {1, dims_in[0], (int64_t)dims_in[0] * dims_in[1]};
   int64_t base = 0;
   for (int j = 0; j < d; ++j)
     if (j != axis) base += o[j] * strides[j];
@@ -722,9 +964,19 @@ __global__ void k_vpass(const T* __restrict__ in, ArrLayout li, T* __restrict__ 
   const int oa = o[axis];
   T s = 0;
   if (!in_bnd_other) {
-    for (int t = lo_[oa]; t < hi_[oa]; ++t) {
-      if (mask_in && (t == 0 || t == nin - 1)) continue;
-      s += M[(int64_t)oa * nin + t] * src[base + t * strides[axis]];
+    // taps in chunks of 8 (predicated): the loads of a chunk are in flight together
+    const int t0 = lo_[oa], t1 = hi_[oa];
+    for (int tb = t0; tb < t1; tb += 8) {
+      T mv[8], xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = tb + u;
+        const bool on = t < t1 && !(mask_in && (t == 0 || t == nin - 1));
+        mv[u] = on ? M[(int64_t)oa * nin + t] : T(0);
+        xv[u] = on ? src[base + t * strides[axis]] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += mv[u] * xv[u];
     }
   }
   if (mask_out)
@@ -827,9 +1079,9 @@ static void space_velocity(const LevelArgs& Li, const LevelArgs& Lo, int nt, int
       ld.level = 0;
       ld.compact_stride = (int64_t)dims[0] * dims[1] * dims[2];
     }
-    int64_t tot = nb * dims[0] * dims[1] * dims[2];
-    k_vpass<T><<<nblk(tot), 256, 0, s>>>(src, ls, dst, ld, nb, d, axis, dims[0], dims[1], dims[2], nin, M, lo, hi,
-                                         axis == 0 ? 1 : 0, (last && restrict_) ? 1 : 0, (last && !restrict_) ? 1 : 0);
+    const dim3 grid(nblk(dims[0], 64), (unsigned)(((dims[1] + 3) / 4) * dims[2]), (unsigned)nb);
+    k_vpass<T><<<grid, 256, 0, s>>>(src, ls, dst, ld, d, axis, dims[0], dims[1], dims[2], nin, M, lo, hi,
+                                    axis == 0 ? 1 : 0, (last && restrict_) ? 1 : 0, (last && !restrict_) ? 1 : 0);
     src = dst;
     ls = ld;
   }
@@ -1013,6 +1265,108 @@ hipError_t launch_dot(const T* a, const T* b, int64_t n, double* partial, double
 template hipError_t launch_dot<double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
 template hipError_t launch_dot<float>(const float*, const float*, int64_t, double*, double*, hipStream_t);
 
+// ---- fused Gram-Schmidt passes, templated on a bound NVM >= nv of the basis
+// size (per-thread accumulators), kFusedBlocks blocks.
+constexpr int kFusedBlocks = 2048;
+
+// Sums of nv values over a block, written to partial[k * kFusedBlocks + block].
+template <int NVM>
+__device__ __forceinline__ void block_sums_out(const double (&acc)[NVM], int nv, double* sh, double* partial) {
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64, nw = blockDim.x / 64;
+#pragma unroll
+  for (int k = 0; k < NVM; ++k) {
+    if (k >= nv) continue;
+    double v = acc[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) sh[k * 4 + wv] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nv; k += blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += sh[k * 4 + i];
+    partial[(int64_t)k * kFusedBlocks + blockIdx.x] = s;
+  }
+}
+
+// partial sums of V_k . w for k < nv (one pass over V and w)
+template <int NVM>
+__global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ V, int64_t ldv, int nv,
+                                              const double* __restrict__ w, int64_t n,
+                                              double* __restrict__ partial) {
+  __shared__ double sh[NVM * 4];
+  double acc[NVM];
+#pragma unroll
+  for (int k = 0; k < NVM; ++k) acc[k] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < NVM; ++k)
+      if (k < nv) acc[k] += V[(int64_t)k * ldv + i] * wi;
+  }
+  block_sums_out<NVM>(acc, nv, sh, partial);
+}
+
+// w -= sum_k h_k V_k, then partial sums of V_k . w (with the updated w) for
+// k < nv (mode 0), or of w . w alone (mode 1)
+template <int NVM>
+__global__ __launch_bounds__(256) void k_axpy_mdot(double* __restrict__ w, const double* __restrict__ V,
+                                                   int64_t ldv, int nv, const double* __restrict__ h, int64_t n,
+                                                   int mode, double* __restrict__ partial) {
+  __shared__ double sh[NVM * 4];
+  double acc[NVM];
+#pragma unroll
+  for (int k = 0; k < NVM; ++k) acc[k] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double vv[NVM];
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NVM; ++k)
+      if (k < nv) {
+        vv[k] = V[(int64_t)k * ldv + i];
+        s += h[k] * vv[k];
+      }
+    const double wi = w[i] - s;
+    w[i] = wi;
+    if (mode == 0) {
+#pragma unroll
+      for (int k = 0; k < NVM; ++k)
+        if (k < nv) acc[k] += vv[k] * wi;
+    } else {
+      acc[0] += wi * wi;
+    }
+  }
+  block_sums_out<NVM>(acc, mode == 0 ? nv : 1, sh, partial);
+}
+
+__global__ void k_fused_final(const double* __restrict__ partial, int nv, double* __restrict__ out) {
+  const int vi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (vi >= nv) return;
+  double s = 0.0;
+  for (int b = 0; b < kFusedBlocks; ++b) s += partial[(int64_t)vi * kFusedBlocks + b];
+  out[vi] = s;
+}
+
+template <int NVM>
+static void cgs2_impl(double* w, const double* V, int64_t ldv, int nv, int64_t n, double* partial, double* dh,
+                      hipStream_t s) {
+  k_mdot<NVM><<<kFusedBlocks, 256, 0, s>>>(V, ldv, nv, w, n, partial);
+  k_fused_final<<<1, 64, 0, s>>>(partial, nv, dh);
+  k_axpy_mdot<NVM><<<kFusedBlocks, 256, 0, s>>>(w, V, ldv, nv, dh, n, 0, partial);
+  k_fused_final<<<1, 64, 0, s>>>(partial, nv, dh + nv);
+  k_axpy_mdot<NVM><<<kFusedBlocks, 256, 0, s>>>(w, V, ldv, nv, dh + nv, n, 1, partial);
+  k_fused_final<<<1, 64, 0, s>>>(partial, 1, dh + 2 * nv);
+}
+
+hipError_t launch_cgs2(double* w, const double* V, int64_t ldv, int nv, int64_t n, double* partial, double* dh,
+                       hipStream_t s) {
+  if (nv < 1 || nv > kMaxFused) return hipErrorInvalidValue;
+  if (nv <= 4) cgs2_impl<4>(w, V, ldv, nv, n, partial, dh, s);
+  else if (nv <= 8) cgs2_impl<8>(w, V, ldv, nv, n, partial, dh, s);
+  else if (nv <= 16) cgs2_impl<16>(w, V, ldv, nv, n, partial, dh, s);
+  else cgs2_impl<32>(w, V, ldv, nv, n, partial, dh, s);
+  return hipGetLastError();
+}
+
 __global__ void k_multi_axpy(double* __restrict__ w, const double* __restrict__ V, int64_t ldv, int nv,
                              const double* __restrict__ h, int64_t n, double sign) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1072,8 +1426,8 @@ hipError_t launch_project_pressure(const LevelArgs& L, const double* mom, double
 
 // explicit instantiations
 #define STMG_INST(T)                                                                                                \
-  template hipError_t launch_apply<T>(const LevelArgs&, const double*, const T*, T, const T*, const T*, const T*,  \
-                                      T*, int, T*, hipStream_t);                                                    \
+  template hipError_t launch_apply<T>(const LevelArgs&, const T*, const T*, const T*, const T*, T*, int, T*,      \
+                                      hipStream_t);                                                                 \
   template hipError_t launch_vanka_factored<T>(const LevelArgs&, const T*, const T*, const T*, const T*, const T*, \
                                                const T*, T*, T, T*, hipStream_t);                                   \
   template hipError_t launch_vanka_dense<T>(const LevelArgs&, const T*, const T*, T*, T, hipStream_t);             \

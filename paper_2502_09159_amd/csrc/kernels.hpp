@@ -13,16 +13,30 @@ struct LevelArgs {
   int64_t nodes, Mv, Mp, slab;
 };
 
+// Cell-local scratch E of the operator and of the smoother: per field
+// f = (n nt + a) d + comp a grid of (Q n)^d duplicated nodes, x fastest, in
+// which local node (ix, iy, iz) of cell (cx, cy, cz) sits at
+// (cx Q + ix, cy Q + iy, cz Q + iz): every cell keeps its own copy of the
+// nodes it shares, and a row of global nodes reads contiguous memory.
+__device__ __forceinline__ int64_t e_index(const LevelArgs& L, int64_t field, int64_t cell, int i) {
+  const int W = L.Q * L.n;
+  const int64_t NE = L.d == 3 ? (int64_t)W * W * W : (int64_t)W * W;
+  const int ix = i % L.Q, iy = (i / L.Q) % L.Q, iz = i / (L.Q * L.Q);
+  const int cx = (int)(cell % L.n), cy = (int)((cell / L.n) % L.n), cz = (int)(cell / ((int64_t)L.n * L.n));
+  return field * NE + (cx * L.Q + ix) + (int64_t)W * ((cy * L.Q + iy) + (int64_t)W * (cz * L.Q + iz));
+}
+
 // Small per-level tables, in the arithmetic type T, packed as
 // [S (QxQ) | Dg (QxQ) | gx (Q) | gw (Q) | K (nt x nt) | phim1 (nt) | coef (nt) | psi (nloc x C)].
 inline int table_size(int Q, int nt, int nloc, int C) { return 2 * Q * Q + 2 * Q + nt * nt + 2 * nt + nloc * C; }
 
-// Operator: y = S x (mode 0) or y = b - S x (mode 1).  Cell contributions to
+// Operator: y = S x (mode 0) or y = b - S x (mode 1).  geo: per-cell Gauss
+// point geometry (apply_geometry layout, in T).  Cell contributions to
 // velocity nodes go to the cell-local scratch E (ncells * d * m * N values)
 // and are summed per node in a fixed order (deterministic, no atomics).
 template <typename T>
-hipError_t launch_apply(const LevelArgs& L, const double* verts, const T* nu_q, T nu_const, const T* tab,
-                        const T* x, const T* b, T* y, int mode, T* E, hipStream_t s);
+hipError_t launch_apply(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y, int mode,
+                        T* E, hipStream_t s);
 
 // Vanka correction with factored local inverses: x += omega D^-1 sum R^T A^-1 R r.
 // Asw: A_s^{-1} of every cell in MFMA operand order (see vanka_swizzle_index),
@@ -81,6 +95,13 @@ hipError_t launch_multidot(const double* V, int64_t ldv, int nv, const double* w
 // partial needs 1024 doubles.
 template <typename T>
 hipError_t launch_dot(const T* a, const T* b, int64_t n, double* partial, double* out, hipStream_t s);
+// Classical Gram-Schmidt with one reorthogonalisation in three passes over
+// the nv <= kMaxFused basis vectors V: h1 = V^T w; w -= V h1 and h2 = V^T w;
+// w -= V h2 and |w|^2.  dh receives h1 (nv), h2 (nv), |w|^2; partial needs
+// nv * 2048 doubles.  All sums in a fixed order.
+constexpr int kMaxFused = 32;
+hipError_t launch_cgs2(double* w, const double* V, int64_t ldv, int nv, int64_t n, double* partial, double* dh,
+                       hipStream_t s);
 // w -= sum_i h_i V_i (h on device)
 hipError_t launch_multi_axpy(double* w, const double* V, int64_t ldv, int nv, const double* h, int64_t n,
                              hipStream_t s);

@@ -311,7 +311,7 @@ __global__ __launch_bounds__(64) void k_net_correction(LevelArgs L, const float*
     const float keep = 1.0f - mask[sidx * 27 + lane];
     for (int a = 0; a < 2; ++a)
       for (int comp = 0; comp < 3; ++comp)
-        E[cell * (int64_t)3 * 2 * 27 * L.N + ((int64_t)(n * 2 + a) * 3 + comp) * 27 + lane] =
+        E[e_index(L, (int64_t)(n * 2 + a) * 3 + comp, cell, lane)] =
             (T)(s * keep * ys[lane * 16 + comp * 2 + a]);
   }
   if (lane < 8) {

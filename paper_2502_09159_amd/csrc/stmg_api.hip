@@ -73,10 +73,8 @@ struct Pool {
 template <typename T>
 struct DevLevel {
   LevelArgs a{};
-  const double* verts = nullptr;  // shared FP64 vertices
-  T* nu_q = nullptr;
-  T nu_const = 1;
   T* tab = nullptr;
+  T* geo = nullptr;  // Gauss-point geometry of the operator kernel
   T *Asw = nullptr, *Bm = nullptr, *F = nullptr, *Hinv = nullptr, *coef = nullptr, *dense = nullptr;
   T* E = nullptr;  // cell-local scratch of the Vanka correction
   T *b = nullptr, *x = nullptr, *r = nullptr;
@@ -140,7 +138,6 @@ struct stmg_ctx {
   hipStream_t stream = nullptr;
   Pool pool;
   std::vector<LevelHost> host;
-  std::vector<double*> verts;
   // FP64 view of every level (operator, per-op calls); FP32 hierarchy in mixed mode
   Hier<double> H64;
   Hier<float> H32;
@@ -194,10 +191,12 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
     const LevelHost& L = c->host[l];
     DevLevel<T>& D = H.L[l];
     D.a = level_args(L);
-    D.verts = c->verts[l];
-    D.nu_const = (T)L.nu_const;
-    if (!L.nu_q.empty()) D.nu_q = c->pool.upload<T>(L.nu_q, s);
     D.tab = c->pool.upload<T>(pack_tables(L), s);
+    {
+      std::vector<double> g;
+      apply_geometry(L, g);
+      D.geo = c->pool.upload<T>(g, s);
+    }
     D.ndofs = L.ndofs;
     // cell-local scratch shared by the operator and the smoother of this level
     D.E = c->pool.alloc<T>((size_t)L.ncells * L.d * L.nt * L.nloc * L.N);
@@ -258,7 +257,7 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
 // ------------------------------------------------------------- level ops
 template <typename T>
 void op_apply(stmg_ctx* c, DevLevel<T>& D, const T* x, const T* b, T* y, int mode) {
-  HIPCHK(launch_apply<T>(D.a, D.verts, D.nu_q, D.nu_const, D.tab, x, b, y, mode, D.E, c->stream));
+  HIPCHK(launch_apply<T>(D.a, D.geo, D.tab, x, b, y, mode, D.E, c->stream));
 }
 
 template <typename T>
@@ -556,7 +555,6 @@ stmg_status stmg_setup(const stmg_params* p, stmg_ctx** out) {
     coarse_inverse(c->host.back(), cinv, cg);
     c->nd_coarse = c->host.back().ndofs;
     c->Cg = c->pool.upload<double>(cg, c->stream);
-    for (auto& L : c->host) c->verts.push_back(c->pool.upload<double>(L.verts, c->stream));
     c->Cinv = c->pool.upload<double>(cinv, c->stream);
     c->mom0 = c->pool.upload<double>(c->host[0].mom, c->stream);
     c->volume0 = c->host[0].volume;
@@ -751,6 +749,10 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
   int status = STMG_OK;
   int rc = guarded(c, [&] {
     const int64_t n = c->host[0].ndofs;
+    // stride of the Krylov basis: a multiple of 4 KiB plus 2.25 KiB, so that
+    // the vectors read side by side by the Gram-Schmidt passes start at
+    // different offsets modulo large powers of two
+    const int64_t ldv = (n + 511) / 512 * 512 + 288;
     hipStream_t s = c->stream;
     DevLevel<double>& L0 = c->H64.L[0];
     // Krylov basis capacity: bounded by max_it and by free device memory
@@ -758,14 +760,14 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
     if (c->cap < want) {
       size_t fr = 0, tot = 0;
       HIPCHK(hipMemGetInfo(&fr, &tot));
-      int64_t fit = (int64_t)(0.45 * (double)fr / (2.0 * n * sizeof(double)));
+      int64_t fit = (int64_t)(0.45 * (double)fr / (2.0 * ldv * sizeof(double)));
       int cap = (int)std::max<int64_t>(8, std::min<int64_t>(want, fit));
       if (cap > c->cap) {
         if (c->V) { (void)hipFree(c->V); (void)hipFree(c->Z); }
         c->V = nullptr;
         c->Z = nullptr;
-        HIPCHK(hipMalloc(&c->V, (size_t)cap * n * sizeof(double)));
-        HIPCHK(hipMalloc(&c->Z, (size_t)cap * n * sizeof(double)));
+        HIPCHK(hipMalloc(&c->V, (size_t)cap * ldv * sizeof(double)));
+        HIPCHK(hipMalloc(&c->Z, (size_t)cap * ldv * sizeof(double)));
         c->cap = cap;
       }
     }
@@ -798,24 +800,35 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
       g[0] = beta;
       int j = 0;
       while (j < m && total < max_it) {
-        double* vj = c->V + (size_t)j * n;
-        double* zj = c->Z + (size_t)j * n;
+        double* vj = c->V + (size_t)j * ldv;
+        double* zj = c->Z + (size_t)j * ldv;
         precondition(c, vj, zj);
-        double* wv = c->V + (size_t)(j + 1) * n;
+        double* wv = c->V + (size_t)(j + 1) * ldv;
         if (c->phase_timing) c->t_op.a(s);
         op_apply<double>(c, L0, zj, zj, wv, 0);
         if (c->phase_timing) c->t_op.b(s);
-        // CGS2
+        // classical Gram-Schmidt, twice (CGS2)
         std::fill(hv.begin(), hv.end(), 0.0);
-        for (int pass = 0; pass < 2; ++pass) {
-          HIPCHK(launch_multidot(c->V, n, j + 1, wv, n, c->partial, c->dh, s));
-          HIPCHK(launch_multi_axpy(wv, c->V, n, j + 1, c->dh, n, s));
-          std::vector<double> hh(j + 1);
-          HIPCHK(hipMemcpyAsync(hh.data(), c->dh, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        double hn;
+        if (j + 1 <= kMaxFused) {
+          // three fused passes over the basis; one host synchronisation
+          HIPCHK(launch_cgs2(wv, c->V, ldv, j + 1, n, c->partial, c->dh, s));
+          std::vector<double> hh(2 * (j + 1) + 1);
+          HIPCHK(hipMemcpyAsync(hh.data(), c->dh, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
           HIPCHK(hipStreamSynchronize(s));
-          for (int i = 0; i <= j; ++i) hv[i] += hh[i];
+          for (int i = 0; i <= j; ++i) hv[i] = hh[i] + hh[j + 1 + i];
+          hn = std::sqrt(hh[2 * (j + 1)]);
+        } else {
+          for (int pass = 0; pass < 2; ++pass) {
+            HIPCHK(launch_multidot(c->V, ldv, j + 1, wv, n, c->partial, c->dh, s));
+            HIPCHK(launch_multi_axpy(wv, c->V, ldv, j + 1, c->dh, n, s));
+            std::vector<double> hh(j + 1);
+            HIPCHK(hipMemcpyAsync(hh.data(), c->dh, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int i = 0; i <= j; ++i) hv[i] += hh[i];
+          }
+          hn = std::sqrt(dot(c, wv, wv, n));
         }
-        double hn = std::sqrt(dot(c, wv, wv, n));
         hv[j + 1] = hn;
         for (int i = 0; i < j; ++i) {
           double t = cs[i] * hv[i] + sn[i] * hv[i + 1];
@@ -843,7 +856,7 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
         y[i] = t / H[(size_t)i * m + i];
       }
       HIPCHK(hipMemcpyAsync(c->dh, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-      HIPCHK(launch_combine(x, c->Z, n, j, c->dh, n, s));
+      HIPCHK(launch_combine(x, c->Z, ldv, j, c->dh, n, s));
     }
     HIPCHK(launch_project_pressure(L0.a, c->mom0, c->volume0, x, c->partial, s));
     HIPCHK(hipEventRecord(e1, s));
