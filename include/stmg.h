@@ -171,10 +171,12 @@ typedef struct {
 } stmg_solve_info;
 
 /* FGMRES (right preconditioned by stmg_vcycle, CGS2, x0 = 0) on the finest
- * level until ||b - S x|| <= rtol ||b|| (explicitly rechecked).  Returns
+ * level until ||b - S x|| <= rtol ||b|| (explicitly rechecked), restarted
+ * every STMG_RESTART iterations (fewer if device memory is short).  Returns
  * STMG_ENOCONV if max_it preconditioner applications were not enough (x then
  * holds the last iterate).  info may be NULL.  The returned x has mean-zero
  * pressure in every slice. */
+#define STMG_RESTART 64
 stmg_status stmg_solve(stmg_ctx* ctx, const double* b, double* x, double rtol, int max_it,
                        stmg_solve_info* info);
 

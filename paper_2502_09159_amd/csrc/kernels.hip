@@ -622,53 +622,80 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
 #pragma unroll
       for (int j = 0; j < 4; ++j) f[kb][j] = At[kb * 256 + j];
   };
-  if (wave < NKB) load_tile(wave, fa[0]);
 
-  // ---- R in B-operand order (padded rows / columns zero), B and the
-  // pressure residual: all loads of this phase are issued before any LDS store
+  // ---- R in B-operand order, B and the pressure residual.  R is read one
+  // x-row of a cell (Q consecutive nodes, one vector load) per item: items
+  // (row, a, comp, n); Dirichlet entries are zeroed in registers.  Padding
+  // entries of R (K >= M or column >= d N) are zeroed separately.  Loads
+  // complete in issue order, so the loads this phase waits for are issued
+  // first, then the A_s^{-1} fragments of the first row tile (consumed only
+  // after the barrier).
   {
-    constexpr int PER = MP * DNP / 256;  // entries of R per thread
+    constexpr int ROWS = NL / Q;                           // x-rows of a cell
+    constexpr int IMAX = (ROWS * NT * D * 8 + 255) / 256;  // items per thread (N <= 8)
     constexpr int PB = (C * D * NL + 255) / 256;
+    const int nitems = ROWS * NT * DN;
     const T* Bc = Bm + cell * (int64_t)C * D * NL;
-    T rv[PER], bv[PB];
+    T rv[IMAX][Q], bv[PB];
+    bool rok[IMAX];
+    // unconditional loads from clamped (in-bounds) addresses, selected later:
+    // the wait counts before the first LDS store then stay exact
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int idx = tid + 256 * e;  // position in RZ
+    for (int e = 0; e < IMAX; ++e) {
+      const int it = min(tid + 256 * e, nitems - 1);
+      const int row = it % ROWS, rest = it / ROWS;  // rest = (a, col)
+      const int a = rest % NT, col = rest / NT;
+      const int comp = col >> lgN, n = col & (N - 1);
+      const int iy = row % Q, iz = row / Q;
+      const int gy = cc[1] * (Q - 1) + iy, gz = D == 3 ? cc[2] * (Q - 1) + iz : 1;
+      rok[e] = tid + 256 * e < nitems && gy > 0 && gy < L.nn - 1 && gz > 0 && (D == 2 || gz < L.nn - 1);
+      const int64_t g = (int64_t)cc[0] * (Q - 1) + (int64_t)L.nn * (gy + (D == 3 ? (int64_t)L.nn * gz : 0));
+      __builtin_memcpy(rv[e], r + vidx(L, n, a, comp, g), sizeof(T) * Q);
+    }
+#pragma unroll
+    for (int e = 0; e < PB; ++e) bv[e] = Bc[min(tid + 256 * e, C * D * NL - 1)];
+    constexpr int PR = (P * 8 + 255) / 256;
+    T pv[PR];
+#pragma unroll
+    for (int e = 0; e < PR; ++e) {
+      const int t = min(tid + 256 * e, P * N - 1), q = t >> lgN, n = t & (N - 1);
+      pv[e] = r[pidx(L, n, q / C, cell, q % C)];
+    }
+    const T cv = coef[min(tid, NT - 1)];
+    load_tile(min(wave, NKB - 1), fa[0]);
+    // padding entries
+    for (int idx = tid; idx < MP * DNP; idx += 256) {
       const int r4 = idx & 3, u = idx >> 2, l64 = u & 63;
       const int K = ((u >> 6) % NKB) * 16 + 4 * (l64 >> 4) + r4;
       const int col = (u >> 6) / NKB * 16 + (l64 & 15);
-      rv[e] = T(0);
-      if (K < M && col < DN) {
-        const int a = K / NL, i = K % NL;
-        const int comp = col >> lgN, n = col & (N - 1);
-        const int ij[3] = {i % Q, (i / Q) % Q, i / (Q * Q)};
-        bool fr = true;
-        int64_t g = 0, st = 1;
+      if (K >= M || col >= DN) RZ[idx] = T(0);
+    }
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-          const int gj = cc[j] * (Q - 1) + ij[j];
-          if (gj == 0 || gj == L.nn - 1) fr = false;
-          g += gj * st;
-          st *= L.nn;
+    for (int e = 0; e < IMAX; ++e) {
+      const int it = tid + 256 * e;
+      if (it < nitems) {
+        const int row = it % ROWS, rest = it / ROWS;
+        const int a = rest % NT, col = rest / NT;
+        const int K0 = a * NL + row * Q;
+        const int ct = col / 16, jj = col % 16;
+        // Dirichlet rows, and Dirichlet nodes at the ends of the row (x = 0, x = 1)
+#pragma unroll
+        for (int j = 0; j < Q; ++j)
+          if (!rok[e] || (j == 0 && cc[0] == 0) || (j == Q - 1 && cc[0] == L.n - 1)) rv[e][j] = T(0);
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          const int K = K0 + j, kb = K / 16, rem = K % 16;
+          RZ[((ct * NKB + kb) * 64 + jj + 16 * (rem / 4)) * 4 + (rem % 4)] = rv[e][j];
         }
-        if (fr) rv[e] = r[vidx(L, n, a, comp, g)];
       }
     }
 #pragma unroll
-    for (int e = 0; e < PB; ++e) {
-      const int t = tid + 256 * e;
-      bv[e] = t < C * D * NL ? Bc[t] : T(0);
-    }
-#pragma unroll
-    for (int e = 0; e < PER; ++e) RZ[tid + 256 * e] = rv[e];
-#pragma unroll
     for (int e = 0; e < PB; ++e)
       if (tid + 256 * e < C * D * NL) sB[tid + 256 * e] = bv[e];
-  }
-  if (tid < NT) sc[tid] = coef[tid];
-  for (int t = tid; t < P * N; t += 256) {
-    const int q = t >> lgN, n = t & (N - 1);
-    Rp[q * N + n] = r[pidx(L, n, q / C, cell, q % C)];
+#pragma unroll
+    for (int e = 0; e < PR; ++e)
+      if (tid + 256 * e < P * N) Rp[tid + 256 * e] = pv[e];
+    if (tid < NT) sc[tid] = cv;
   }
   __syncthreads();
 
@@ -710,18 +737,20 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
   constexpr int HPT = (P * 8 + 255) / 256;  // (pp, n) items per thread, N <= 8
   const T* Fc = F + cell * (int64_t)D * M * P;
   const T* H = Hinv + cell * (int64_t)P * P;
-  T fv[RPT][P], hv[HPT][P];
-#pragma unroll
-  for (int j = 0; j < RPT; ++j) {
-    const int row2 = tid + 256 * j;
-#pragma unroll
-    for (int q = 0; q < P; ++q) fv[j][q] = row2 < D * M ? Fc[((row2 / M) * P + q) * M + row2 % M] : T(0);
-  }
+  T fv[RPT][P], hv[HPT][P], xp[HPT];
+  // (unconditional loads from clamped addresses: exact wait counts)
 #pragma unroll
   for (int j = 0; j < HPT; ++j) {
-    const int t = tid + 256 * j, pp = t >> lgN;
+    const int t = min(tid + 256 * j, P * N - 1), pp = t >> lgN, n = t & (N - 1);
 #pragma unroll
-    for (int q = 0; q < P; ++q) hv[j][q] = t < P * N ? H[q * P + pp] : T(0);
+    for (int q = 0; q < P; ++q) hv[j][q] = H[q * P + pp];
+    xp[j] = x[pidx(L, n, pp / C, cell, pp % C)];
+  }
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) {
+    const int row2 = min(tid + 256 * j, D * M - 1);
+#pragma unroll
+    for (int q = 0; q < P; ++q) fv[j][q] = Fc[((row2 / M) * P + q) * M + row2 % M];
   }
   __syncthreads();
   const T* Z = RZ;
@@ -746,7 +775,7 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
 #pragma unroll
       for (int q = 0; q < P; ++q) s += hv[j][q] * S[q * N + n];
       YP[pp * N + n] = s;
-      x[pidx(L, n, pp / C, cell, pp % C)] += omega * s;
+      x[pidx(L, n, pp / C, cell, pp % C)] = xp[j] + omega * s;
     }
   }
   __syncthreads();
@@ -934,57 +963,86 @@ __device__ __forceinline__ int64_t arr_base(const ArrLayout& A, int64_t b64) {
   return (int64_t)n * A.slab + (int64_t)a * A.Mv + (int64_t)comp * A.nodes;
 }
 
-// out[b][..o..] (+)= sum_t M[o][t] in[b][..t..] along `axis`;
-// dims_out (dx, dy, dz), nin = extent of the input along the axis.  Launch:
-// 64 x 4 threads per block, grid (ceil(dx/64), ceil(dy/4) dz, nb).
-template <typename T>
+// out[b][..o..] (+)= sum_t M[o][t] in[b][..t..] along `axis` (nonzero range
+// [lo_[o], hi_[o]) of at most MAXT taps; M stored banded and transposed,
+// M[u * nout + o] = M(o, lo_[o] + u)); dims_out (dx, dy, dz), nin = extent
+// of the input along the axis.  Launch: 64 x 4 threads per block, each thread
+// ZC consecutive outputs along the slowest direction (z in 3D, y in 2D); grid
+// (ceil(dx/64), ceil(dy/4) ceil(dz/ZC) (3D) or ceil(dy/(4 ZC)) (2D), nb).
+// Taps are read unconditionally from clamped, in-bounds positions and weighted
+// by zero when outside the row, so all loads of a thread are in flight together.
+template <typename T, int MAXT>
 __global__ __launch_bounds__(256) void k_vpass(const T* __restrict__ in, ArrLayout li, T* __restrict__ out,
                                                ArrLayout lo, int d, int axis, int dx, int dy, int dz, int nin,
                                                const T* __restrict__ M, const int* __restrict__ lo_,
                                                const int* __restrict__ hi_, int mask_in, int mask_out,
                                                int accumulate) {
-  const int bx = blockIdx.x, by = blockIdx.y;
+  constexpr int ZC = 8;
   const int64_t b = blockIdx.z;
-  const int ny4 = (dy + 3) / 4;
-  const int o[3] = {bx * 64 + (int)(threadIdx.x & 63), (by % ny4) * 4 + (int)(threadIdx.x >> 6), by / ny4};
-  if (o[0] >= dx || o[1] >= dy) return;
-  const int64_t e = o[0] + (int64_t)dx * (o[1] + (int64_t)dy * o[2]);
+  const int ox = blockIdx.x * 64 + (int)(threadIdx.x & 63);
+  int oy, oz0;
+  if (d == 3) {
+    const int ny4 = (dy + 3) / 4;
+    oy = ((int)blockIdx.y % ny4) * 4 + (int)(threadIdx.x >> 6);
+    oz0 = ((int)blockIdx.y / ny4) * ZC;
+  } else {
+    oy = ((int)blockIdx.y * 4 + (int)(threadIdx.x >> 6)) * ZC;
+    oz0 = 0;
+  }
+  if (ox >= dx || oy >= dy) return;
   const int dims_out[3] = {dx, dy, dz};
   int dims_in[3] = {dx, dy, dz};
   dims_in[axis] = nin;
   const T* src = in + arr_base(li, b);
+  T* dst = out + arr_base(lo, b);
   const int64_t strides[3] = {1, dims_in[0], (int64_t)dims_in[0] * dims_in[1]};
-  int64_t base = 0;
-  for (int j = 0; j < d; ++j)
-    if (j != axis) base += o[j] * strides[j];
-  bool in_bnd_other = false;
-  if (mask_in)
-    for (int j = 0; j < d; ++j)
-      if (j != axis && (o[j] == 0 || o[j] == dims_in[j] - 1)) in_bnd_other = true;
-  const int oa = o[axis];
-  T s = 0;
-  if (!in_bnd_other) {
-    // taps in chunks of 8 (predicated): the loads of a chunk are in flight together
-    const int t0 = lo_[oa], t1 = hi_[oa];
-    for (int tb = t0; tb < t1; tb += 8) {
-      T mv[8], xv[8];
+  const int slow = d == 3 ? 2 : 1;  // the direction walked by the thread
+  T res[ZC];
+  int64_t eo[ZC];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int t = tb + u;
-        const bool on = t < t1 && !(mask_in && (t == 0 || t == nin - 1));
-        mv[u] = on ? M[(int64_t)oa * nin + t] : T(0);
-        xv[u] = on ? src[base + t * strides[axis]] : T(0);
+  for (int k = 0; k < ZC; ++k) {
+    int o[3] = {ox, oy, oz0};
+    o[slow] += k;
+    res[k] = T(0);
+    eo[k] = -1;
+    if (o[slow] >= dims_out[slow]) continue;
+    eo[k] = o[0] + (int64_t)dx * (o[1] + (int64_t)dy * o[2]);
+    int64_t base = 0;
+    bool in_bnd_other = false;
+    for (int j = 0; j < d; ++j)
+      if (j != axis) {
+        base += o[j] * strides[j];
+        if (mask_in && (o[j] == 0 || o[j] == dims_in[j] - 1)) in_bnd_other = true;
+      }
+    // along y and z the tap row is the same for the whole wave: make it uniform
+    // (scalar loads of the range and the coefficients)
+    const int oa = axis == 0 ? o[0] : __builtin_amdgcn_readfirstlane(o[axis]);
+    const int t0 = lo_[oa], t1 = hi_[oa];
+    T s = 0;
+    if (!in_bnd_other && t1 > t0) {
+      T mv[MAXT], xv[MAXT];
+#pragma unroll
+      for (int u = 0; u < MAXT; ++u) {
+        const int t = min(t0 + u, t1 - 1);
+        const bool on = t0 + u < t1 && !(mask_in && (t == 0 || t == nin - 1));
+        mv[u] = M[u * dims_out[axis] + oa];  // banded, transposed table
+        xv[u] = src[base + t * strides[axis]];
+        if (!on) mv[u] = T(0);
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s += mv[u] * xv[u];
+      for (int u = 0; u < MAXT; ++u) s += mv[u] * xv[u];
     }
+    if (mask_out)
+      for (int j = 0; j < d; ++j)
+        if (o[j] == 0 || o[j] == dims_out[j] - 1) s = 0;
+    res[k] = s;
   }
-  if (mask_out)
-    for (int j = 0; j < d; ++j)
-      if (o[j] == 0 || o[j] == dims_out[j] - 1) s = 0;
-  T* dst = out + arr_base(lo, b) + e;
-  if (accumulate) *dst += s;
-  else *dst = s;
+#pragma unroll
+  for (int k = 0; k < ZC; ++k) {
+    if (eo[k] < 0) continue;
+    if (accumulate) dst[eo[k]] += res[k];
+    else dst[eo[k]] = res[k];
+  }
 }
 
 // Pressure: prolong (dir 0): xf[cf][l] += sum_m E[pos][l][m] xc[parent][m];
@@ -1061,27 +1119,41 @@ static inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs
 
 template <typename T>
 static void space_velocity(const LevelArgs& Li, const LevelArgs& Lo, int nt, int N, const T* M, const int* lo,
-                           const int* hi, const T* in, ArrLayout li, T* out, ArrLayout lout, T* tmp1, T* tmp2,
-                           bool restrict_, hipStream_t s) {
-  // Li: spatial sizes of the input, Lo: of the output
+                           const int* hi, int max_row, const T* in, ArrLayout li, T* out, ArrLayout lout, T* tmp1,
+                           T* tmp2, bool restrict_, hipStream_t s) {
+  // Li: spatial sizes of the input, Lo: of the output.  Prolongation runs the
+  // passes x, y, z and restriction z, y, x, so that the x pass (whose taps
+  // differ from lane to lane) always works on the coarse side of the
+  // intermediate arrays.
   const int d = Li.d;
   const int64_t nb = (int64_t)N * nt * d;
   int dims[3] = {Li.nn, Li.nn, d == 3 ? Li.nn : 1};
   const T* src = in;
   ArrLayout ls = li;
-  for (int axis = 0; axis < d; ++axis) {
+  for (int pass = 0; pass < d; ++pass) {
+    const int axis = restrict_ ? d - 1 - pass : pass;
     int nin = dims[axis];
     dims[axis] = Lo.nn;
-    bool last = axis == d - 1;
-    T* dst = last ? out : (axis == 0 ? tmp1 : tmp2);
+    bool last = pass == d - 1;
+    T* dst = last ? out : (pass == 0 ? tmp1 : tmp2);
     ArrLayout ld = lout;
     if (!last) {
       ld.level = 0;
       ld.compact_stride = (int64_t)dims[0] * dims[1] * dims[2];
     }
-    const dim3 grid(nblk(dims[0], 64), (unsigned)(((dims[1] + 3) / 4) * dims[2]), (unsigned)nb);
-    k_vpass<T><<<grid, 256, 0, s>>>(src, ls, dst, ld, d, axis, dims[0], dims[1], dims[2], nin, M, lo, hi,
-                                    axis == 0 ? 1 : 0, (last && restrict_) ? 1 : 0, (last && !restrict_) ? 1 : 0);
+    const unsigned gy = d == 3 ? (unsigned)(((dims[1] + 3) / 4) * ((dims[2] + 7) / 8))
+                               : (unsigned)((dims[1] + 31) / 32);
+    const dim3 grid(nblk(dims[0], 64), gy, (unsigned)nb);
+    const int mi = pass == 0 ? 1 : 0, mo = (last && restrict_) ? 1 : 0, acc = (last && !restrict_) ? 1 : 0;
+    if (max_row <= 4)
+      k_vpass<T, 4><<<grid, 256, 0, s>>>(src, ls, dst, ld, d, axis, dims[0], dims[1], dims[2], nin, M, lo, hi, mi,
+                                          mo, acc);
+    else if (max_row <= 8)
+      k_vpass<T, 8><<<grid, 256, 0, s>>>(src, ls, dst, ld, d, axis, dims[0], dims[1], dims[2], nin, M, lo, hi, mi,
+                                          mo, acc);
+    else
+      k_vpass<T, 16><<<grid, 256, 0, s>>>(src, ls, dst, ld, d, axis, dims[0], dims[1], dims[2], nin, M, lo, hi, mi,
+                                           mo, acc);
     src = dst;
     ls = ld;
   }
@@ -1104,7 +1176,7 @@ hipError_t launch_prolongate_add(const LevelArgs& F, const LevelArgs& Cs, const 
   }
   ArrLayout li{1, nt_src, F.d, slab_src, Cs.Mv, Cs.nodes, 0};
   ArrLayout lo{1, F.nt, F.d, F.slab, F.Mv, F.nodes, 0};
-  space_velocity<T>(Cs, F, F.nt, F.N, P1, rlo, rhi, src, li, xf, lo, tmp1, tmp2, false, s);
+  space_velocity<T>(Cs, F, F.nt, F.N, P1, rlo, rhi, t.max_row_p1, src, li, xf, lo, tmp1, tmp2, false, s);
   int64_t tot = (int64_t)F.N * F.nt * (int64_t)(F.Mp);
   k_ppass<T><<<nblk(tot), 256, 0, s>>>(src, xf, F.N * F.nt, nt_src, F.nt, slab_src, (int64_t)nt_src * Cs.Mv, Cs.Mp,
                                        F.slab, (int64_t)F.nt * F.Mv, F.Mp, F.d, F.n, Cs.n, F.C, Cs.C, E, t.npos, 0,
@@ -1120,7 +1192,7 @@ hipError_t launch_restrict(const LevelArgs& F, const LevelArgs& Cs, const Transf
   int64_t slab_dst = t.time_change ? (int64_t)F.nt * (Cs.Mv + Cs.Mp) : Cs.slab;
   ArrLayout li{1, F.nt, F.d, F.slab, F.Mv, F.nodes, 0};
   ArrLayout lo{1, F.nt, F.d, slab_dst, Cs.Mv, Cs.nodes, 0};
-  space_velocity<T>(F, Cs, F.nt, F.N, P1T, clo, chi, rf, li, dst, lo, tmp1, tmp2, true, s);
+  space_velocity<T>(F, Cs, F.nt, F.N, P1T, clo, chi, t.max_row_p1t, rf, li, dst, lo, tmp1, tmp2, true, s);
   int64_t ncc = 1;
   for (int j = 0; j < F.d; ++j) ncc *= Cs.n;
   int64_t tot = (int64_t)F.N * F.nt * ncc * Cs.C;
@@ -1265,16 +1337,18 @@ hipError_t launch_dot(const T* a, const T* b, int64_t n, double* partial, double
 template hipError_t launch_dot<double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
 template hipError_t launch_dot<float>(const float*, const float*, int64_t, double*, double*, hipStream_t);
 
-// ---- fused Gram-Schmidt passes, templated on a bound NVM >= nv of the basis
-// size (per-thread accumulators), kFusedBlocks blocks.
+// ---- Gram-Schmidt passes of the Arnoldi process (lagged CGS2), templated on
+// a bound NVM of the number of basis vectors (per-thread accumulators; the
+// basis values of one element are kept in registers for NVM <= 32 and read
+// again otherwise), kFusedBlocks blocks, sums in a fixed order.
 constexpr int kFusedBlocks = 2048;
 
 // Sums of nv values over a block, written to partial[k * kFusedBlocks + block].
-template <int NVM>
-__device__ __forceinline__ void block_sums_out(const double (&acc)[NVM], int nv, double* sh, double* partial) {
+template <int NA>
+__device__ __forceinline__ void block_sums_out(const double (&acc)[NA], int nv, double* sh, double* partial) {
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64, nw = blockDim.x / 64;
 #pragma unroll
-  for (int k = 0; k < NVM; ++k) {
+  for (int k = 0; k < NA; ++k) {
     if (k >= nv) continue;
     double v = acc[k];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -1288,54 +1362,78 @@ __device__ __forceinline__ void block_sums_out(const double (&acc)[NVM], int nv,
   }
 }
 
-// partial sums of V_k . w for k < nv (one pass over V and w)
+// First pass of a step with j final basis vectors V_0..V_{j-1} and a pending
+// vector u with second-projection coefficients h2 and norm 1/invb:
+//   V_j = (u - sum_{k<j} h2_k V_k) invb   (written; skipped when pending == 0)
+//   partial sums of V_k . w for k <= j (k < j when pending == 0).
 template <int NVM>
-__global__ __launch_bounds__(256) void k_mdot(const double* __restrict__ V, int64_t ldv, int nv,
-                                              const double* __restrict__ w, int64_t n,
-                                              double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_lcgs_a(double* __restrict__ V, int64_t ldv, int j, int pending,
+                                                const double* __restrict__ u, const double* __restrict__ h2,
+                                                double invb, const double* __restrict__ w, int64_t n,
+                                                double* __restrict__ partial) {
+  constexpr bool KEEP = NVM <= 32;
   __shared__ double sh[NVM * 4];
   double acc[NVM];
 #pragma unroll
   for (int k = 0; k < NVM; ++k) acc[k] = 0.0;
+  const int nf = pending ? j : j + 1;  // final vectors read
+  double* vj = V + (int64_t)j * ldv;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double vv[KEEP ? NVM : 1];
     const double wi = w[i];
+    double s = 0.0;
 #pragma unroll
     for (int k = 0; k < NVM; ++k)
-      if (k < nv) acc[k] += V[(int64_t)k * ldv + i] * wi;
+      if (k < nf) {
+        const double vk = V[(int64_t)k * ldv + i];
+        if constexpr (KEEP) vv[k] = vk;
+        if (pending) s += h2[k] * vk;
+        acc[k] += vk * wi;
+      }
+    if (pending) {
+      const double vn = (u[i] - s) * invb;
+      vj[i] = vn;
+#pragma unroll
+      for (int k = 0; k < NVM; ++k)
+        if (k == j) acc[k] += vn * wi;
+    }
   }
-  block_sums_out<NVM>(acc, nv, sh, partial);
+  block_sums_out<NVM>(acc, j + 1, sh, partial);
 }
 
-// w -= sum_k h_k V_k, then partial sums of V_k . w (with the updated w) for
-// k < nv (mode 0), or of w . w alone (mode 1)
+// Second pass: w -= sum_{k<nv} h_k V_k, then partial sums of V_k . w (updated
+// w) for k < nv and of w . w (index nv).
 template <int NVM>
 __global__ __launch_bounds__(256) void k_axpy_mdot(double* __restrict__ w, const double* __restrict__ V,
                                                    int64_t ldv, int nv, const double* __restrict__ h, int64_t n,
-                                                   int mode, double* __restrict__ partial) {
-  __shared__ double sh[NVM * 4];
-  double acc[NVM];
+                                                   double* __restrict__ partial) {
+  constexpr bool KEEP = NVM <= 32;
+  __shared__ double sh[(NVM + 1) * 4];
+  double acc[NVM + 1];
 #pragma unroll
-  for (int k = 0; k < NVM; ++k) acc[k] = 0.0;
+  for (int k = 0; k <= NVM; ++k) acc[k] = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double vv[NVM];
+    double vv[KEEP ? NVM : 1];
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < NVM; ++k)
       if (k < nv) {
-        vv[k] = V[(int64_t)k * ldv + i];
-        s += h[k] * vv[k];
+        const double vk = V[(int64_t)k * ldv + i];
+        if constexpr (KEEP) vv[k] = vk;
+        s += h[k] * vk;
       }
     const double wi = w[i] - s;
     w[i] = wi;
-    if (mode == 0) {
 #pragma unroll
-      for (int k = 0; k < NVM; ++k)
-        if (k < nv) acc[k] += vv[k] * wi;
-    } else {
-      acc[0] += wi * wi;
-    }
+    for (int k = 0; k < NVM; ++k)
+      if (k < nv) acc[k] += (KEEP ? vv[KEEP ? k : 0] : V[(int64_t)k * ldv + i]) * wi;
+    acc[NVM] += wi * wi;
   }
-  block_sums_out<NVM>(acc, mode == 0 ? nv : 1, sh, partial);
+  // move the norm next to the nv dot products
+  double out[NVM + 1];
+#pragma unroll
+  for (int k = 0; k <= NVM; ++k) out[k] = k == nv ? acc[NVM] : acc[k];
+  block_sums_out<NVM + 1>(out, nv + 1, sh, partial);
 }
 
 __global__ void k_fused_final(const double* __restrict__ partial, int nv, double* __restrict__ out) {
@@ -1347,23 +1445,26 @@ __global__ void k_fused_final(const double* __restrict__ partial, int nv, double
 }
 
 template <int NVM>
-static void cgs2_impl(double* w, const double* V, int64_t ldv, int nv, int64_t n, double* partial, double* dh,
-                      hipStream_t s) {
-  k_mdot<NVM><<<kFusedBlocks, 256, 0, s>>>(V, ldv, nv, w, n, partial);
-  k_fused_final<<<1, 64, 0, s>>>(partial, nv, dh);
-  k_axpy_mdot<NVM><<<kFusedBlocks, 256, 0, s>>>(w, V, ldv, nv, dh, n, 0, partial);
-  k_fused_final<<<1, 64, 0, s>>>(partial, nv, dh + nv);
-  k_axpy_mdot<NVM><<<kFusedBlocks, 256, 0, s>>>(w, V, ldv, nv, dh + nv, n, 1, partial);
-  k_fused_final<<<1, 64, 0, s>>>(partial, 1, dh + 2 * nv);
+static void lcgs2_impl(double* V, int64_t ldv, int j, int pending, const double* u, const double* h2_prev,
+                       double invb, double* w, int64_t n, double* partial, double* h1, double* h2n,
+                       hipStream_t s) {
+  const int nv = j + 1;
+  k_lcgs_a<NVM><<<kFusedBlocks, 256, 0, s>>>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial);
+  k_fused_final<<<1, 64, 0, s>>>(partial, nv, h1);
+  k_axpy_mdot<NVM><<<kFusedBlocks, 256, 0, s>>>(w, V, ldv, nv, h1, n, partial);
+  k_fused_final<<<2, 64, 0, s>>>(partial, nv + 1, h2n);
 }
 
-hipError_t launch_cgs2(double* w, const double* V, int64_t ldv, int nv, int64_t n, double* partial, double* dh,
-                       hipStream_t s) {
-  if (nv < 1 || nv > kMaxFused) return hipErrorInvalidValue;
-  if (nv <= 4) cgs2_impl<4>(w, V, ldv, nv, n, partial, dh, s);
-  else if (nv <= 8) cgs2_impl<8>(w, V, ldv, nv, n, partial, dh, s);
-  else if (nv <= 16) cgs2_impl<16>(w, V, ldv, nv, n, partial, dh, s);
-  else cgs2_impl<32>(w, V, ldv, nv, n, partial, dh, s);
+hipError_t launch_lcgs2(double* V, int64_t ldv, int j, int pending, const double* u, const double* h2_prev,
+                        double invb, double* w, int64_t n, double* partial, double* h1, double* h2n,
+                        hipStream_t s) {
+  const int nv = j + 1;
+  if (j < 0 || nv > kMaxFused || (!pending && j != 0)) return hipErrorInvalidValue;
+  if (nv <= 4) lcgs2_impl<4>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial, h1, h2n, s);
+  else if (nv <= 8) lcgs2_impl<8>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial, h1, h2n, s);
+  else if (nv <= 16) lcgs2_impl<16>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial, h1, h2n, s);
+  else if (nv <= 32) lcgs2_impl<32>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial, h1, h2n, s);
+  else lcgs2_impl<64>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial, h1, h2n, s);
   return hipGetLastError();
 }
 

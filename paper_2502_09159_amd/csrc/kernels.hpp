@@ -58,11 +58,15 @@ hipError_t launch_vanka_gather_only(const LevelArgs& L, const T* E, T* x, T omeg
 template <typename T>
 hipError_t launch_vanka_dense(const LevelArgs& L, const T* Ainv, const T* r, T* x, T omega, hipStream_t s);
 
-// Transfers.  Tables (device): P1 (nnf x nnc), P1T (nnc x nnf) row-major with
-// nonzero ranges; E (npos x Cf x Cc); Pt (ntf x ntc) row-major.
+// Transfers.  Tables (device): the 1D velocity embedding P1 (nnf x nnc) and
+// its transpose P1T, each with the nonzero range [lo, hi) of every row and
+// stored banded and transposed: P1[u * nnf + g] = P1(g, lo(g) + u) for u < 16
+// (zero past the row), likewise P1T with nnc rows; E (npos x Cf x Cc); Pt
+// (ntf x ntc) row-major.
 struct TransferDev {
   int nnf, nnc, npos, ntf, ntc;
   bool time_change;
+  int max_row_p1, max_row_p1t;  // longest nonzero range of a row of P1 / P1T
 };
 template <typename T>
 hipError_t launch_prolongate_add(const LevelArgs& F, const LevelArgs& Cs, const TransferDev& t,
@@ -95,13 +99,19 @@ hipError_t launch_multidot(const double* V, int64_t ldv, int nv, const double* w
 // partial needs 1024 doubles.
 template <typename T>
 hipError_t launch_dot(const T* a, const T* b, int64_t n, double* partial, double* out, hipStream_t s);
-// Classical Gram-Schmidt with one reorthogonalisation in three passes over
-// the nv <= kMaxFused basis vectors V: h1 = V^T w; w -= V h1 and h2 = V^T w;
-// w -= V h2 and |w|^2.  dh receives h1 (nv), h2 (nv), |w|^2; partial needs
-// nv * 2048 doubles.  All sums in a fixed order.
-constexpr int kMaxFused = 32;
-hipError_t launch_cgs2(double* w, const double* V, int64_t ldv, int nv, int64_t n, double* partial, double* dh,
-                       hipStream_t s);
+// One Arnoldi step of classical Gram-Schmidt with one reorthogonalisation,
+// lagged by one step (two passes over the basis).  On entry V_0..V_{j-1} are
+// final; if pending, u holds the previous step's vector after its first
+// projection, with second-projection coefficients h2_prev (device) and norm
+// 1/invb.  Pass 1 writes V_j = (u - V h2_prev) invb (if pending) and h1 =
+// V_{0..j}^T w; pass 2 does w -= V h1 and writes h2n = (V^T w, |w|^2), nv + 1
+// values with nv = j + 1.  Without a pending vector j must be 0 (V_0 final).
+// partial needs (nv + 1) * 2048 doubles; nv <= kMaxFused.  Sums in a fixed
+// order.
+constexpr int kMaxFused = 64;
+hipError_t launch_lcgs2(double* V, int64_t ldv, int j, int pending, const double* u, const double* h2_prev,
+                        double invb, double* w, int64_t n, double* partial, double* h1, double* h2n,
+                        hipStream_t s);
 // w -= sum_i h_i V_i (h on device)
 hipError_t launch_multi_axpy(double* w, const double* V, int64_t ldv, int nv, const double* h, int64_t n,
                              hipStream_t s);

@@ -147,7 +147,8 @@ struct stmg_ctx {
   double* mom0 = nullptr;  // finest-level pressure moments
   double volume0 = 1.0;
   // FGMRES work
-  double *V = nullptr, *Z = nullptr, *w = nullptr, *partial = nullptr, *dh = nullptr, *dtmp = nullptr;
+  double *V = nullptr, *Z = nullptr, *w = nullptr, *u = nullptr, *partial = nullptr, *dh = nullptr,
+         *dtmp = nullptr;
   int cap = 0;
   std::vector<double> history;
   bool phase_timing = false;
@@ -232,11 +233,25 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
     DevTransfer<T>& X = H.X[l];
     X.t.nnf = T0.nnf; X.t.nnc = T0.nnc; X.t.npos = T0.npos; X.t.ntf = T0.ntf; X.t.ntc = T0.ntc;
     X.t.time_change = T0.time_change;
+
     std::vector<double> P1T((size_t)T0.nnc * T0.nnf);
     for (int g = 0; g < T0.nnf; ++g)
       for (int h = 0; h < T0.nnc; ++h) P1T[(size_t)h * T0.nnf + g] = T0.P1[(size_t)g * T0.nnc + h];
-    X.P1 = c->pool.upload<T>(T0.P1, s);
-    X.P1T = c->pool.upload<T>(P1T, s);
+    X.t.max_row_p1 = X.t.max_row_p1t = 0;
+    for (int g = 0; g < T0.nnf; ++g) X.t.max_row_p1 = std::max(X.t.max_row_p1, T0.row_hi[g] - T0.row_lo[g]);
+    for (int h = 0; h < T0.nnc; ++h) X.t.max_row_p1t = std::max(X.t.max_row_p1t, T0.col_hi[h] - T0.col_lo[h]);
+    if (X.t.max_row_p1 > 16 || X.t.max_row_p1t > 16)
+      throw Error(STMG_EUNSUPPORTED, "transfer rows longer than 16 taps");
+    // banded, transposed: Mb[u][row] = M[row][lo(row) + u], u < 16 (zero past the row)
+    std::vector<double> P1b((size_t)16 * T0.nnf, 0.0), P1Tb((size_t)16 * T0.nnc, 0.0);
+    for (int g = 0; g < T0.nnf; ++g)
+      for (int u = 0; u < T0.row_hi[g] - T0.row_lo[g]; ++u)
+        P1b[(size_t)u * T0.nnf + g] = T0.P1[(size_t)g * T0.nnc + T0.row_lo[g] + u];
+    for (int h = 0; h < T0.nnc; ++h)
+      for (int u = 0; u < T0.col_hi[h] - T0.col_lo[h]; ++u)
+        P1Tb[(size_t)u * T0.nnc + h] = P1T[(size_t)h * T0.nnf + T0.col_lo[h] + u];
+    X.P1 = c->pool.upload<T>(P1b, s);
+    X.P1T = c->pool.upload<T>(P1Tb, s);
     X.rlo = c->pool.upload<int>(T0.row_lo, s);
     X.rhi = c->pool.upload<int>(T0.row_hi, s);
     X.clo = c->pool.upload<int>(T0.col_lo, s);
@@ -566,6 +581,7 @@ stmg_status stmg_setup(const stmg_params* p, stmg_ctx** out) {
     c->partial = c->pool.alloc<double>((ns + 128) * 520 + 1024 * 128);
     c->dh = c->pool.alloc<double>(1024);
     c->w = c->pool.alloc<double>(c->host[0].ndofs);
+    c->u = c->pool.alloc<double>(c->host[0].ndofs);
     c->dtmp = c->pool.alloc<double>(c->host[0].ndofs);
     // release host element matrices (kept: level sizes and tables)
     for (auto& L : c->host) {
@@ -756,7 +772,8 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
     hipStream_t s = c->stream;
     DevLevel<double>& L0 = c->H64.L[0];
     // Krylov basis capacity: bounded by max_it and by free device memory
-    int want = std::min(max_it, 100) + 1;
+    static_assert(STMG_RESTART <= kMaxFused, "restart length beyond the fused Gram-Schmidt kernels");
+    int want = std::min(max_it, STMG_RESTART) + 1;
     if (c->cap < want) {
       size_t fr = 0, tot = 0;
       HIPCHK(hipMemGetInfo(&fr, &tot));
@@ -799,36 +816,36 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       int j = 0;
+      // Arnoldi with classical Gram-Schmidt twice, lagged by one step: the
+      // new direction u (after its first projection) is preconditioned as
+      // it stands (FGMRES admits any z_j, and the V-cycle is homogeneous);
+      // its second projection and normalisation are applied by the first
+      // pass of the next step, which writes the final V_j.
+      double* wv = c->w;
+      double* uv = c->u;
+      double invb = 0.0;
       while (j < m && total < max_it) {
-        double* vj = c->V + (size_t)j * ldv;
         double* zj = c->Z + (size_t)j * ldv;
-        precondition(c, vj, zj);
-        double* wv = c->V + (size_t)(j + 1) * ldv;
+        precondition(c, j == 0 ? c->V : uv, zj);
         if (c->phase_timing) c->t_op.a(s);
         op_apply<double>(c, L0, zj, zj, wv, 0);
         if (c->phase_timing) c->t_op.b(s);
-        // classical Gram-Schmidt, twice (CGS2)
+        double* h1 = c->dh;
+        double* h2n = c->dh + 256 + 128 * (j & 1);
+        const double* h2p = c->dh + 256 + 128 * ((j + 1) & 1);
+        HIPCHK(launch_lcgs2(c->V, ldv, j, j > 0 ? 1 : 0, uv, h2p, invb, wv, n, c->partial, h1, h2n, s));
+        std::vector<double> hh(j + 1), h2(j + 2);
+        HIPCHK(hipMemcpyAsync(hh.data(), h1, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h2.data(), h2n, h2.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
         std::fill(hv.begin(), hv.end(), 0.0);
-        double hn;
-        if (j + 1 <= kMaxFused) {
-          // three fused passes over the basis; one host synchronisation
-          HIPCHK(launch_cgs2(wv, c->V, ldv, j + 1, n, c->partial, c->dh, s));
-          std::vector<double> hh(2 * (j + 1) + 1);
-          HIPCHK(hipMemcpyAsync(hh.data(), c->dh, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-          HIPCHK(hipStreamSynchronize(s));
-          for (int i = 0; i <= j; ++i) hv[i] = hh[i] + hh[j + 1 + i];
-          hn = std::sqrt(hh[2 * (j + 1)]);
-        } else {
-          for (int pass = 0; pass < 2; ++pass) {
-            HIPCHK(launch_multidot(c->V, ldv, j + 1, wv, n, c->partial, c->dh, s));
-            HIPCHK(launch_multi_axpy(wv, c->V, ldv, j + 1, c->dh, n, s));
-            std::vector<double> hh(j + 1);
-            HIPCHK(hipMemcpyAsync(hh.data(), c->dh, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            for (int i = 0; i <= j; ++i) hv[i] += hh[i];
-          }
-          hn = std::sqrt(dot(c, wv, wv, n));
+        double q2 = 0.0;
+        for (int i = 0; i <= j; ++i) {
+          hv[i] = hh[i] + h2[i];
+          q2 += h2[i] * h2[i];
         }
+        // |w - V h2| from |w|^2 - |h2|^2 (h2 is a rounding-level correction)
+        const double hn = std::sqrt(std::max(0.0, h2[j + 1] - q2));
         hv[j + 1] = hn;
         for (int i = 0; i < j; ++i) {
           double t = cs[i] * hv[i] + sn[i] * hv[i + 1];
@@ -848,7 +865,8 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
         c->history.push_back(std::fabs(g[j]) / bnorm);
         if (!std::isfinite(g[j])) throw Error(STMG_ESINGULAR, "FGMRES produced a non-finite residual");
         if (std::fabs(g[j]) <= rtol * bnorm || hn == 0.0) break;
-        HIPCHK(launch_scale_copy(wv, wv, 1.0 / hn, n, s));
+        invb = 1.0 / hn;
+        std::swap(wv, uv);  // the projected w becomes the pending direction
       }
       for (int i = j - 1; i >= 0; --i) {
         double t = g[i];

@@ -76,6 +76,7 @@ _sig = {
                               ctypes.POINTER(ctypes.c_double)],
 }
 NET_PARAMS = 52704
+RESTART = 64  # STMG_RESTART: FGMRES restart length of stmg_solve
 for _name, _args in _sig.items():
     _f = getattr(lib, _name)
     _f.argtypes = _args

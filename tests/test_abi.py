@@ -36,6 +36,14 @@ def test_binding_covers_the_header():
     assert set(declared_functions()) <= set(stmg.EXPORTED)
 
 
+def test_binding_constants_match_the_header():
+    from paper_2502_09159_amd import stmg
+    text = open(os.path.join(ROOT, "include", "stmg.h")).read()
+    defines = dict(re.findall(r"#define\s+(STMG_[A-Z_]+)\s+(\d+)", text))
+    assert int(defines["STMG_RESTART"]) == stmg.RESTART
+    assert int(defines["STMG_NET_PARAMS"]) == stmg.NET_PARAMS
+
+
 def test_hierarchy_matches_oracle_rule():
     from oracle.hierarchy import build_levels
     from paper_2502_09159_amd import stmg

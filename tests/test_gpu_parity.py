@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 import torch
 
+from paper_2502_09159_amd.stmg import RESTART
 from gpu_common import CONFIGS, announce, dev, host, make_solver, oracle_mg, rel, rhs
 
 pytestmark = pytest.mark.gpu
@@ -139,7 +140,7 @@ def test_solve_iterations_and_solution(name):
     for rtol in (1e-8, 1e-10):
         x = torch.empty(len(b), dtype=torch.float64, device="cuda")
         info = g.solve(dev(b), x, rtol=rtol, max_it=100)
-        xo, it, hist = fgmres(L.apply, o.vcycle, b, rtol=rtol, max_it=100)
+        xo, it, hist = fgmres(L.apply, o.vcycle, b, rtol=rtol, max_it=100, restart=RESTART)
         announce(f"solve {name} rtol {rtol}: gpu {info['iterations']} oracle {it}")
         assert info["iterations"] == it
         assert info["rel_residual"] <= rtol
