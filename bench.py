@@ -43,20 +43,70 @@ def solver_params(w, precision):
     return p
 
 
-def vanka_bytes(w, ncells_fine, elem_bytes):
-    """Algorithmic bytes of one Vanka correction on the finest level: the
-    stored factors of every cell (A_s^{-1}: m^2, B: C d nl, F: d m P, H^{-1}: P^2)
-    plus one read of r and one read+write of x."""
+def element_sizes(w):
     from math import comb
     d, r, k, N = w["dim"], w["r"], w["k"], w["n_sub"]
     nl = (r + 2) ** d
     nt = k + 1
     C = comb(r + d, d)
-    m, P = nt * nl, nt * C
-    factors = m * m + C * d * nl + d * m * P + P * P
     n = w["n_cells_1d"]
-    ndofs = N * nt * (d * (n * (r + 1) + 1) ** d + n ** d * C)
-    return (ncells_fine * factors + 3 * ndofs) * elem_bytes
+    ncells = n ** d
+    ndofs = N * nt * (d * (n * (r + 1) + 1) ** d + ncells * C)
+    return d, nl, nt, C, N, ncells, ndofs
+
+
+def vanka_local_bytes(w, elem_bytes):
+    """Algorithmic bytes of the Vanka local solves on the finest level (the
+    kernel k_vanka_mfma): the stored factors of every cell (A_s^{-1} padded to
+    16: mp^2, B: C d nl, F: d m P, H^{-1}: P^2), one read of the residual,
+    the cell-local velocity corrections written once, and the pressure
+    unknowns read and written once."""
+    d, nl, nt, C, N, ncells, ndofs = element_sizes(w)
+    m, P = nt * nl, nt * C
+    mp = (m + 15) // 16 * 16
+    factors = mp * mp + C * d * nl + d * m * P + P * P
+    corrections = ncells * d * m * N
+    pressure = 2 * ncells * C * nt * N
+    return (ncells * factors + ndofs + corrections + pressure) * elem_bytes
+
+
+def apply_cell_flops(w):
+    """Floating-point operations of the operator's cell kernel on the finest
+    level, counting every sum-factorized contraction once (an FMA is 2 flops):
+    per cell and subinterval, the interpolation of the d(k+1) velocity fields
+    (3 contractions of Q^4 FMAs each), then per (component, temporal dof) the
+    mass/jump term (k+2 FMAs a point), the reference gradient (3 contractions),
+    the flux with the metric and pressure (about 5d FMAs a point), the
+    transposed gradient and interpolation (6 contractions), plus the pressure
+    interpolation and the divergence test (C FMAs a point each, per temporal
+    dof)."""
+    d, nl, nt, C, N, ncells, ndofs = element_sizes(w)
+    Q = w["r"] + 2
+    contraction = nl * Q  # one 1D contraction of a cell
+    interp = d * nt * d * contraction
+    per_field = nl * (nt + 1) + d * contraction + nl * 5 * d + 2 * d * contraction
+    pres = 2 * nt * nl * C
+    return 2.0 * ncells * N * (interp + d * nt * per_field + pres)
+
+
+def measured_traffic(kernel_prefix, grid):
+    """Scaled HBM bytes per launch of a kernel from the counter summary kept
+    in profiles/ (FETCH_SIZE and WRITE_SIZE runs), or None when the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_counters.json")
+    src = os.path.join(ROOT, "paper_2502_09159_amd", "csrc", "kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_hip_sha256") != sha:
+        return None
+    for k in rec.get("kernels", []):
+        if k["name"].startswith(kernel_prefix) and k["grid"] == grid:
+            return k["fetch_bytes"] + k["write_bytes"]
+    return None
 
 
 def cpu_baseline(w):
@@ -100,7 +150,7 @@ def main():
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (multi-GPU sharding is a design, not built)",
+        print("bench.py: measures one GPU only (the solver is not sharded across GPUs)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -147,24 +197,40 @@ def main():
     value = ndofs / (t / args.steps)
     print(f"[bench] timed: {ms_per_step:.1f} ms/solve, {its} it", file=sys.stderr, flush=True)
 
-    # dominant kernel: the Vanka correction on the finest level, event-timed
-    # on the stream the library launches on (torch's current stream)
+    # dominant kernel: the Vanka local solves on the finest level
+    # (k_vanka_mfma), event-timed on the stream the library launches on
+    # (torch's current stream); the library's own event timing is reported beside
     stream = torch.cuda.current_stream()
     reps = 10
+    elem = 4 if prec == stmg.MIXED_FP32 else 8
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    lib_ms = S.kernel_time(0, level=0, reps=reps)
+    lib_ms = S.kernel_time(2, level=0, reps=reps)
     e1.record(stream)
     torch.cuda.synchronize()
     ev_ms = e0.elapsed_time(e1) / reps
-    elem = 4 if prec == stmg.MIXED_FP32 else 8
-    ncell = w["n_cells_1d"] ** w["dim"]
-    nbytes = vanka_bytes(w, ncell, elem)
-    achieved = nbytes / (lib_ms * 1e-3) / 1e9
+    nbytes = vanka_local_bytes(w, elem)
+    achieved = nbytes / (ev_ms * 1e-3) / 1e9
+    d_, nl_, nt_, C_, N_, ncells_, _ = element_sizes(w)
+    traffic = measured_traffic("k_vanka_mfma", ncells_ * 256)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_vanka_mfma + k_vanka_gather (finest level)", "ms_per_launch_group": round(lib_ms, 4),
-                "ms_event_bracket": round(ev_ms, 4), "algorithmic_bytes": nbytes}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_vanka_mfma (finest level, local solves of every cell)",
+                "ms_per_launch": round(ev_ms, 4), "ms_library_events": round(lib_ms, 4),
+                "algorithmic_bytes": nbytes}
+    # the operator's cell kernel on the finest level (ALU-bound: flops of the
+    # sum-factorized evaluation over its event-timed duration)
+    e0.record(stream)
+    cell_ms = S.kernel_time(3, level=0, reps=reps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    cell_ev_ms = e0.elapsed_time(e1) / reps
+    flops = apply_cell_flops(w)
+    alu_peak = 157.3 if elem == 4 else 78.6
+    roofline_apply = {"bound": "alu", "achieved": round(flops / (cell_ev_ms * 1e-3) / 1e12, 2), "peak": alu_peak,
+                      "unit": "TFLOP/s", "frac": round(flops / (cell_ev_ms * 1e-3) / 1e12 / alu_peak, 4),
+                      "kernel": "k_apply (finest level, cell kernel)", "ms_per_launch": round(cell_ev_ms, 4),
+                      "ms_library_events": round(cell_ms, 4), "flops": flops}
     op_ms = S.kernel_time(1, level=0, reps=reps)
 
     extra = {}
@@ -206,7 +272,7 @@ def main():
                              + (", learned correction on Q2/P1 x DG(1) levels" if args.variant == "learned" else ""),
                    "iterations": its[-1], "setup_s": round(setup_s, 2),
                    "operator_residual_ms": round(op_ms, 4), **extra},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "roofline_apply": roofline_apply, "cpu_baseline": cpu,
     }
     S.close()
     print(json.dumps(line), flush=True)

@@ -136,11 +136,12 @@ stmg_status stmg_smooth(stmg_ctx* ctx, int level, const double* b, double* x, in
 stmg_status stmg_vanka_correction(stmg_ctx* ctx, int level, const double* r, double* x);
 
 /* Benchmark helper: run one kernel class `reps` times back to back on the
- * level's internal work vectors, in the context's precision, on the
- * context's stream, and return the mean device time of one application in
- * *avg_ms (HIP events).  which = 0: Vanka correction (all colours);
- * which = 1: operator residual b - S x (all colours).  The work vectors'
- * contents are overwritten. */
+ * level's internal work vectors, in the context's precision (the V-cycle's),
+ * on the context's stream, and return the mean device time of one
+ * application in *avg_ms (HIP events).  which = 0: Vanka correction (local
+ * solves and node gather); 1: operator residual b - S x (cell kernel and node
+ * gather); 2: the Vanka local solves alone (factored smoother only); 3: the
+ * operator's cell kernel alone.  The work vectors' contents are overwritten. */
 stmg_status stmg_kernel_time(stmg_ctx* ctx, int which, int level, int reps, double* avg_ms);
 
 /* coarse = P^T fine (restriction, App. A) from `level` to `level + 1`. */

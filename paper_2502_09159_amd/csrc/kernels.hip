@@ -524,7 +524,7 @@ static hipError_t node_gather(const LevelArgs& L, const T* E, const T* xin, cons
 
 template <typename T, int D, int Q, int NT>
 static hipError_t apply_impl(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y,
-                             int mode, T* E, hipStream_t s) {
+                             int mode, T* E, hipStream_t s, bool gather) {
   constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
   if (L.C != C || L.nt != NT || L.Q != Q || L.nodes >= (int64_t(1) << 31)) return hipErrorInvalidValue;
   const int64_t ncells = L.Mp / L.C;
@@ -536,15 +536,15 @@ static hipError_t apply_impl(const LevelArgs& L, const T* geo, const T* tab, con
   k_apply<T, D, Q, NT><<<dim3((unsigned)nbx, (unsigned)nchunk), 256, 0, s>>>(L, geo, tab, x, b, y,
                                                                                              E, mode, nper);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !gather) return e;
   return node_gather<T, 0>(L, E, x, b, y, mode, T(0), s);
 }
 
 template <typename T>
 hipError_t launch_apply(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y, int mode,
-                        T* E, hipStream_t s) {
+                        T* E, hipStream_t s, bool gather) {
 #define STMG_AP(DD, QQ, NN) \
-  if (L.d == DD && L.Q == QQ && L.nt == NN) return apply_impl<T, DD, QQ, NN>(L, geo, tab, x, b, y, mode, E, s);
+  if (L.d == DD && L.Q == QQ && L.nt == NN) return apply_impl<T, DD, QQ, NN>(L, geo, tab, x, b, y, mode, E, s, gather);
   STMG_AP(2, 3, 1) STMG_AP(2, 3, 2) STMG_AP(2, 3, 3) STMG_AP(2, 3, 4)
   STMG_AP(2, 4, 1) STMG_AP(2, 4, 2) STMG_AP(2, 4, 3) STMG_AP(2, 4, 4)
   STMG_AP(3, 3, 1) STMG_AP(3, 3, 2) STMG_AP(3, 3, 3) STMG_AP(3, 3, 4)
@@ -809,7 +809,7 @@ static hipError_t vanka_gather(const LevelArgs& L, const T* E, T* x, T omega, hi
 
 template <typename T, int D, int Q, int NT>
 static hipError_t vanka_fact_impl(const LevelArgs& L, const T* Asw, const T* Bm, const T* F, const T* Hinv,
-                                  const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s) {
+                                  const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s, bool gather) {
   constexpr int NL = D == 3 ? Q * Q * Q : Q * Q;
   constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
   constexpr int M = NT * NL, MP = (M + 15) / 16 * 16, P = NT * C;
@@ -835,6 +835,7 @@ static hipError_t vanka_fact_impl(const LevelArgs& L, const T* Asw, const T* Bm,
     return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
+  if (!gather) return hipGetLastError();
   return vanka_gather<T>(L, E, x, omega, s);
 }
 
@@ -845,9 +846,9 @@ hipError_t launch_vanka_gather_only(const LevelArgs& L, const T* E, T* x, T omeg
 
 template <typename T>
 hipError_t launch_vanka_factored(const LevelArgs& L, const T* Asw, const T* Bm, const T* F, const T* Hinv,
-                                 const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s) {
+                                 const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s, bool gather) {
 #define STMG_VF(DD, QQ, KK) \
-  if (L.d == DD && L.Q == QQ && L.nt == KK) return vanka_fact_impl<T, DD, QQ, KK>(L, Asw, Bm, F, Hinv, coef, r, x, omega, E, s);
+  if (L.d == DD && L.Q == QQ && L.nt == KK) return vanka_fact_impl<T, DD, QQ, KK>(L, Asw, Bm, F, Hinv, coef, r, x, omega, E, s, gather);
   STMG_VF(2, 3, 1) STMG_VF(2, 3, 2) STMG_VF(2, 3, 3) STMG_VF(2, 3, 4)
   STMG_VF(2, 4, 1) STMG_VF(2, 4, 2) STMG_VF(2, 4, 3) STMG_VF(2, 4, 4)
   STMG_VF(3, 3, 1) STMG_VF(3, 3, 2) STMG_VF(3, 3, 3) STMG_VF(3, 3, 4)
@@ -1528,9 +1529,9 @@ hipError_t launch_project_pressure(const LevelArgs& L, const double* mom, double
 // explicit instantiations
 #define STMG_INST(T)                                                                                                \
   template hipError_t launch_apply<T>(const LevelArgs&, const T*, const T*, const T*, const T*, T*, int, T*,      \
-                                      hipStream_t);                                                                 \
+                                      hipStream_t, bool);                                                           \
   template hipError_t launch_vanka_factored<T>(const LevelArgs&, const T*, const T*, const T*, const T*, const T*, \
-                                               const T*, T*, T, T*, hipStream_t);                                   \
+                                               const T*, T*, T, T*, hipStream_t, bool);                             \
   template hipError_t launch_vanka_dense<T>(const LevelArgs&, const T*, const T*, T*, T, hipStream_t);             \
   template hipError_t launch_prolongate_add<T>(const LevelArgs&, const LevelArgs&, const TransferDev&, const T*,   \
                                                const int*, const int*, const T*, const T*, const T*, T*, T*, T*,    \

@@ -35,16 +35,20 @@ inline int table_size(int Q, int nt, int nloc, int C) { return 2 * Q * Q + 2 * Q
 // velocity nodes go to the cell-local scratch E (ncells * d * m * N values)
 // and are summed per node in a fixed order (deterministic, no atomics).
 template <typename T>
+// gather = false runs the cell kernel only (E written, y's pressure rows
+// written, velocity rows untouched): for timing.
 hipError_t launch_apply(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y, int mode,
-                        T* E, hipStream_t s);
+                        T* E, hipStream_t s, bool gather = true);
 
 // Vanka correction with factored local inverses: x += omega D^-1 sum R^T A^-1 R r.
 // Asw: A_s^{-1} of every cell in MFMA operand order (see vanka_swizzle_index),
 // padded to mp = 16 ceil(m/16); E: cell-local scratch of ncells * d * m * N
 // values (the velocity corrections, summed per node by a gather kernel).
 template <typename T>
+// gather = false runs the local solves only (E and the pressure updates): for timing.
 hipError_t launch_vanka_factored(const LevelArgs& L, const T* Asw, const T* Bm, const T* F, const T* Hinv,
-                                 const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s);
+                                 const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s,
+                                 bool gather = true);
 // Position of A_s^{-1}[row][k] inside one cell's swizzled block (mp x mp):
 // row tile t = row/16, k chunk kb = k/16, lane = row%16 + 16*((k%16)/4), slot k%4.
 inline int64_t vanka_swizzle_index(int mp, int row, int k) {

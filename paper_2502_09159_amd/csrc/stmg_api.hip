@@ -675,7 +675,8 @@ stmg_status stmg_vanka_correction(stmg_ctx* c, int level, const double* r, doubl
 stmg_status stmg_kernel_time(stmg_ctx* c, int which, int level, int reps, double* avg_ms) {
   if (!c || !avg_ms || reps < 1 || level < 0 || level >= (int)c->host.size()) return STMG_EINVAL;
   if (which == 0 && level + 1 >= (int)c->host.size()) return STMG_EINVAL;
-  if (which != 0 && which != 1) return STMG_EINVAL;
+  if (which < 0 || which > 3) return STMG_EINVAL;
+  if (which == 2 && (level + 1 >= (int)c->host.size() || c->p.vanka_mode != STMG_VANKA_FACTORED)) return STMG_EINVAL;
   return (stmg_status)guarded(c, [&] {
     auto run = [&](auto& D) {
       using T = std::remove_reference_t<decltype(*D.x)>;
@@ -688,7 +689,12 @@ stmg_status stmg_kernel_time(stmg_ctx* c, int which, int level, int reps, double
       HIPCHK(hipEventRecord(e0, c->stream));
       for (int i = 0; i < reps; ++i) {
         if (which == 0) op_vanka<T>(c, D, D.r, D.x);
-        else op_apply<T>(c, D, D.x, D.b, D.r, 1);
+        else if (which == 1) op_apply<T>(c, D, D.x, D.b, D.r, 1);
+        else if (which == 2)
+          HIPCHK(launch_vanka_factored<T>(D.a, D.Asw, D.Bm, D.F, D.Hinv, D.coef, D.r, D.x, (T)c->p.omega, D.E,
+                                          c->stream, false));
+        else
+          HIPCHK(launch_apply<T>(D.a, D.geo, D.tab, D.x, D.b, D.r, 1, D.E, c->stream, false));
       }
       HIPCHK(hipEventRecord(e1, c->stream));
       HIPCHK(hipEventSynchronize(e1));
@@ -698,8 +704,7 @@ stmg_status stmg_kernel_time(stmg_ctx* c, int which, int level, int reps, double
       (void)hipEventDestroy(e1);
       *avg_ms = ms / reps;
     };
-    if (c->mixed && which == 0) run(c->H32.L[level]);
-    else if (c->mixed) run(c->H32.L[level]);
+    if (c->mixed) run(c->H32.L[level]);
     else run(c->H64.L[level]);
   });
 }
