@@ -18,6 +18,35 @@ def quad_rule(d, npts):
     return el.tensor_points(x1, d), el.tensor_weights(w1, d)
 
 
+def reference_tables(d, r):
+    """Gauss rule with r+2 points per direction, velocity basis values and
+    reference gradients, pressure basis values at those points."""
+    xq, wq = quad_rule(d, r + 2)
+    phi, dphi = el.velocity_basis(d, r, xq)
+    psi = el.pressure_values(d, r, xq)
+    return xq, wq, phi, dphi, psi
+
+
+def cell_matrices(mesh, c, ref, nu):
+    """Element matrices of cell c: mass, viscous Laplacian (nu inside),
+    divergence B[l, comp, node], pressure mass, pressure moments, volume."""
+    xq, wq, phi, dphi, psi = ref
+    x, J = mesh.map(c, xq)
+    det = np.linalg.det(J)
+    if np.any(det <= 0):
+        raise ValueError("inverted cell")
+    Jinv = np.linalg.inv(J)                    # [p, j, i] = dxi_j/dx_i
+    nuq = nu(x) if callable(nu) else np.full(len(wq), float(nu))
+    jxw = det * wq
+    grad = np.einsum("pij,pnj->pni", np.transpose(Jinv, (0, 2, 1)), dphi)  # physical grads
+    Me = np.einsum("p,pa,pb->ab", jxw, phi, phi)
+    Ae = np.einsum("p,pai,pbi->ab", jxw * nuq, grad, grad)
+    Be = np.einsum("p,pl,pni->lin", jxw, psi, grad)
+    Mpe = np.einsum("p,pl,pm->lm", jxw, psi, psi)
+    moments = np.einsum("p,pl->l", jxw, psi)
+    return Me, Ae, Be, Mpe, moments, jxw.sum()
+
+
 class SpatialLevel:
     """All spatial data of one (mesh, r) pair.
 
@@ -41,32 +70,17 @@ class SpatialLevel:
 
     # ------------------------------------------------------------ elements
     def _element_matrices(self):
-        d, r = self.d, self.r
-        xq, wq = quad_rule(d, r + 2)
-        phi, dphi = el.velocity_basis(d, r, xq)
-        psi = el.pressure_values(d, r, xq)
-        nc, nl, C = self.mesh.n_cells, self.nloc, self.C
+        d, nc, nl, C = self.d, self.mesh.n_cells, self.nloc, self.C
         self.Me = np.zeros((nc, nl, nl))
         self.Ae = np.zeros((nc, nl, nl))
         self.Be = np.zeros((nc, C, d, nl))   # B[l, comp, node]
         self.Mpe = np.zeros((nc, C, C))
         self.moments = np.zeros((nc, C))     # int_K psi_l dx
         self.volume = np.zeros(nc)
+        ref = reference_tables(d, self.r)
         for c in range(nc):
-            x, J = self.mesh.map(c, xq)
-            det = np.linalg.det(J)
-            if np.any(det <= 0):
-                raise ValueError("inverted cell")
-            Jinv = np.linalg.inv(J)                    # [p, j, i] = dxi_j/dx_i
-            nu = self.nu(x) if callable(self.nu) else np.full(len(wq), float(self.nu))
-            jxw = det * wq
-            grad = np.einsum("pij,pnj->pni", np.transpose(Jinv, (0, 2, 1)), dphi)  # physical grads
-            self.Me[c] = np.einsum("p,pa,pb->ab", jxw, phi, phi)
-            self.Ae[c] = np.einsum("p,pai,pbi->ab", jxw * nu, grad, grad)
-            self.Be[c] = np.einsum("p,pl,pni->lin", jxw, psi, grad)
-            self.Mpe[c] = np.einsum("p,pl,pm->lm", jxw, psi, psi)
-            self.moments[c] = np.einsum("p,pl->l", jxw, psi)
-            self.volume[c] = jxw.sum()
+            (self.Me[c], self.Ae[c], self.Be[c], self.Mpe[c], self.moments[c],
+             self.volume[c]) = cell_matrices(self.mesh, c, ref, self.nu)
 
     # ------------------------------------------------------------ globals
     def _assemble(self):
