@@ -194,8 +194,9 @@ class Solver:
         _check(lib.stmg_vanka_correction(self.ctx, level, _ptr(r, n), _ptr(x, n)), self.ctx)
 
     def kernel_time(self, which, level=0, reps=10):
-        """Mean device time (ms) of one application of kernel class `which`
-        (0: Vanka correction, 1: operator residual) on `level`."""
+        """Mean device time (ms) of one application of kernel class `which` on
+        `level`: 0 Vanka correction, 1 operator residual, 2 the Vanka local
+        solves alone, 3 the operator's cell kernel alone."""
         ms = ctypes.c_double()
         _check(lib.stmg_kernel_time(self.ctx, which, level, reps, ctypes.byref(ms)), self.ctx)
         return ms.value
