@@ -196,7 +196,11 @@ stmg_status stmg_project_pressure_mean_zero(stmg_ctx* ctx, double* x);
  * accumulation.  The correction c is added with the step alpha = <r, S c> /
  * <S c, S c> that minimises the level's residual 2-norm, so it cannot raise
  * it; if alpha <= 0 the correction is skipped and the network is switched
- * off for the rest of the solve.
+ * off for the rest of the solve.  A level with another element whose next
+ * coarser level has the network's element on the same mesh (e.g. the finest
+ * Q3/P2 x DG(1) level above the Q2/P1 x DG(1) level) takes the correction
+ * P c_coarse(P^T r) through that level: residual restricted, network
+ * correction there, prolongated (App. A transfers), then the same step.
  * Weights: STMG_NET_PARAMS FP32 values, W1 (32x15x27), W2 (32x32x27),
  * W3 (14x32x27), each [c_out][c_in][offset], offset (dx+1)+3(dy+1)+9(dz+1).
  * ------------------------------------------------------------------------ */
@@ -206,7 +210,9 @@ stmg_status stmg_project_pressure_mean_zero(stmg_ctx* ctx, double* x);
 stmg_status stmg_learned_load(stmg_ctx* ctx, const float* weights_host, size_t n);
 /* Read the current weights back (e.g. after training). */
 stmg_status stmg_learned_weights(const stmg_ctx* ctx, float* weights_host, size_t n);
-/* Switch the correction on/off inside stmg_vcycle / stmg_solve. */
+/* Switch the correction inside stmg_vcycle / stmg_solve: on = 0 off; 1 on
+ * every level it reaches (directly or through the next level); 2 only on
+ * levels with the network's element. */
 stmg_status stmg_learned_enable(stmg_ctx* ctx, int on);
 
 /* Training pairs on the finest level (3D, r=1, k=1): run the first V-cycle
@@ -224,8 +230,11 @@ stmg_status stmg_learned_record(stmg_ctx* ctx, const double* b, const double* xs
 stmg_status stmg_learned_train(stmg_ctx* ctx, const float* r_pairs, const float* e_pairs, int n_pairs,
                                uint64_t seed, int epochs, int batch, float lr, float* loss_hist);
 
-/* Test hooks on one level (3D, r=1, k=1), FP64 in and out:
- * u = sum_T R_T^T s_T net(R_T r / s_T) (the correction, no residual check);
+/* Test hooks on one level, FP64 in and out:
+ * u = sum_T R_T^T s_T net(R_T r / s_T) (the correction, no residual check) on
+ * a level with the network's element, or P of it applied to P^T r on a level
+ * that reaches one through the next level (FP64 contexts only);
+ * the gradient on a level with the network's element (3D, r=1, k=1):
  * grad = d/dW [sum |net - e|^2 / sum |e|^2] over all cells of the level. */
 stmg_status stmg_learned_correction(stmg_ctx* ctx, int level, const double* r, double* u);
 stmg_status stmg_learned_gradient(stmg_ctx* ctx, int level, const double* r, const double* e, float* grad_host,

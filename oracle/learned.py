@@ -2,7 +2,8 @@
 
 The paper has no learned component; this follows the network of reading G15:
 per space-time cell T = K x I_n of a 3D level with the Q2/P1 x DG(1) element
-(r = 1, k = 1), the cell residual becomes a 15-channel tensor on the 3x3x3
+(r = 1, k = 1; other levels reach it through the next level, see
+`correction_through`), the cell residual becomes a 15-channel tensor on the 3x3x3
 Gauss-Lobatto nodes:
   channels 0..5  : velocity residual, channel comp*2 + a (component, temporal dof)
   channels 6..13 : pressure residual of mode l at temporal dof a, channel 6 + 4a + l,
@@ -188,6 +189,14 @@ def correction(L: SpaceTimeLevel, Ws, r):
     u /= val
     u[L.dirichlet_mask()] = 0.0
     return u
+
+
+def correction_through(Lc, P, Ws, r):
+    """Reading G15 B on a level whose element is not Q2/P1 x DG(1) but whose
+    next coarser level Lc has it on the same mesh: the residual restricted
+    with the level transfer (App. A), the network correction on Lc, and that
+    correction prolongated back: P correction(Lc, P^T r)."""
+    return P @ correction(Lc, Ws, P.T @ r)
 
 
 def targets(L, e, s):

@@ -156,6 +156,7 @@ struct stmg_ctx {
   // learned correction
   NetDev net;
   bool net_ready = false, learned_on = false, learned_disabled = false;
+  int learned_reading = 1;  // 1: every level reaching a Q2/P1 x DG(1) level on its mesh; 2: those levels only
   std::vector<void*> lsave;  // per level: copy of x before a correction
 };
 
@@ -352,6 +353,25 @@ void net_alloc(stmg_ctx* c, int64_t batch) {
 
 bool net_level(const LevelArgs& a) { return a.d == 3 && a.Q == 3 && a.nt == 2; }
 
+// How the learned correction reaches level l: 1 the level has the network's
+// element; 2 the next coarser level has it, on the same mesh and the same
+// subintervals (the correction is computed there: residual restricted,
+// network correction prolongated); 0 not at all.
+int net_route(const stmg_ctx* c, int l) {
+  const auto& L = c->H64.L;
+  if (net_level(L[l].a)) return 1;
+  if (l + 1 < (int)L.size() && net_level(L[l + 1].a) && L[l + 1].a.n == L[l].a.n && L[l + 1].a.N == L[l].a.N)
+    return 2;
+  return 0;
+}
+
+template <typename T>
+Hier<T>& hier_of(stmg_ctx* c);
+template <>
+Hier<double>& hier_of<double>(stmg_ctx* c) { return c->H64; }
+template <>
+Hier<float>& hier_of<float>(stmg_ctx* c) { return c->H32; }
+
 // u (velocity into E then gathered with weight 1, pressure added) += net correction of r
 template <typename T>
 void net_correct(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x) {
@@ -381,14 +401,36 @@ double dot_t(stmg_ctx* c, const T* a, const T* b, int64_t n) {
   return h;
 }
 
+// cv = the network correction of the residual r on level l (route 1), or
+// P net(P^T r) through the next level (route 2), with the next level's
+// learned work vectors as temporaries
+template <typename T>
+void learned_correction_at(stmg_ctx* c, int level, int route, const T* r, T* cv) {
+  Hier<T>& H = hier_of<T>(c);
+  DevLevel<T>& D = H.L[level];
+  HIPCHK(launch_fill<T>(cv, T(0), D.ndofs, c->stream));
+  if (route == 1) {
+    net_correct<T>(c, D, r, cv);
+    return;
+  }
+  DevLevel<T>& Cl = H.L[level + 1];
+  T* rc = static_cast<T*>(c->lsave[2 * (level + 1)]);
+  T* cc = static_cast<T*>(c->lsave[2 * (level + 1) + 1]);
+  op_restrict<T>(c, H, level, r, rc);
+  HIPCHK(launch_fill<T>(cc, T(0), Cl.ndofs, c->stream));
+  net_correct<T>(c, Cl, rc, cc);
+  op_prolongate_add<T>(c, H, level, cc, cv);
+}
+
 template <typename T>
 void learned_step(stmg_ctx* c, DevLevel<T>& D, int level, const T* b, T* x) {
-  if (!c->learned_on || c->learned_disabled || !c->net_ready || !net_level(D.a)) return;
+  if (!c->learned_on || c->learned_disabled || !c->net_ready) return;
+  const int route = net_route(c, level);
+  if (route == 0 || (route == 2 && c->learned_reading != 1)) return;
   T* cv = static_cast<T*>(c->lsave[2 * level]);
   T* wv = static_cast<T*>(c->lsave[2 * level + 1]);
   op_apply<T>(c, D, x, b, D.r, 1);
-  HIPCHK(launch_fill<T>(cv, T(0), D.ndofs, c->stream));
-  net_correct<T>(c, D, D.r, cv);
+  learned_correction_at<T>(c, level, route, D.r, cv);
   op_apply<T>(c, D, cv, cv, wv, 0);
   const double rw = dot_t<T>(c, D.r, wv, D.ndofs), ww = dot_t<T>(c, wv, wv, D.ndofs);
   if (!(rw > 0.0) || !(ww > 0.0) || !std::isfinite(rw / ww)) {
@@ -932,22 +974,27 @@ stmg_status stmg_learned_weights(const stmg_ctx* cc, float* w, size_t n) {
   });
 }
 
+// learned work vectors (two per level reached by the correction), in the V-cycle's precision
+static void lsave_alloc(stmg_ctx* c) {
+  if (!c->lsave.empty()) return;
+  for (size_t l = 0; l < c->host.size(); ++l) {
+    size_t bytes = (c->mixed ? sizeof(float) : sizeof(double));
+    bool use = net_route(c, (int)l) != 0;
+    c->lsave.push_back(use ? c->pool.alloc<char>(c->host[l].ndofs * bytes) : nullptr);
+    c->lsave.push_back(use ? c->pool.alloc<char>(c->host[l].ndofs * bytes) : nullptr);
+  }
+}
+
 stmg_status stmg_learned_enable(stmg_ctx* c, int on) {
-  if (!c) return STMG_EINVAL;
+  if (!c || on < 0 || on > 2) return STMG_EINVAL;
   if (on && !c->net_ready) {
     c->err = "load weights before enabling the learned correction";
     return STMG_EINVAL;
   }
   return (stmg_status)guarded(c, [&] {
-    if (on && c->lsave.empty()) {
-      for (size_t l = 0; l < c->host.size(); ++l) {
-        size_t bytes = (c->mixed ? sizeof(float) : sizeof(double));
-        bool use = net_level(c->H64.L[l].a);
-        c->lsave.push_back(use ? c->pool.alloc<char>(c->host[l].ndofs * bytes) : nullptr);
-        c->lsave.push_back(use ? c->pool.alloc<char>(c->host[l].ndofs * bytes) : nullptr);
-      }
-    }
+    if (on) lsave_alloc(c);
     c->learned_on = on != 0;
+    if (on) c->learned_reading = on;
   });
 }
 
@@ -1020,11 +1067,15 @@ stmg_status stmg_learned_train(stmg_ctx* c, const float* rp, const float* ep, in
 
 stmg_status stmg_learned_correction(stmg_ctx* c, int level, const double* r, double* u) {
   if (!c || !r || !u || level < 0 || level >= (int)c->host.size() || !c->net_ready) return STMG_EINVAL;
-  if (!net_level(c->H64.L[level].a)) return STMG_EINVAL;
+  const int route = net_route(c, level);
+  if (route == 0) return STMG_EINVAL;
+  if (route == 2 && c->mixed) {
+    c->err = "the correction through the next level is evaluated in an FP64 context";
+    return STMG_EINVAL;
+  }
   return (stmg_status)guarded(c, [&] {
-    DevLevel<double>& D = c->H64.L[level];
-    HIPCHK(launch_fill<double>(u, 0.0, D.ndofs, c->stream));
-    net_correct<double>(c, D, r, u);
+    if (route == 2) lsave_alloc(c);
+    learned_correction_at<double>(c, level, route, r, u);
     HIPCHK(hipStreamSynchronize(c->stream));
   });
 }

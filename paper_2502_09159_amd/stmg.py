@@ -235,8 +235,12 @@ class Solver:
                self.ctx)
         return w
 
-    def learned_enable(self, on=True):
-        _check(lib.stmg_learned_enable(self.ctx, int(on)), self.ctx)
+    def learned_enable(self, on=True, element_levels_only=False):
+        """on: the correction on every level it reaches (directly or through
+        the next level); element_levels_only: only on levels with the
+        network's element."""
+        code = 0 if not on else (2 if element_levels_only else 1)
+        _check(lib.stmg_learned_enable(self.ctx, code), self.ctx)
 
     def learned_record(self, b, xstar):
         n = self.ndofs(0)

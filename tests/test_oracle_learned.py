@@ -81,3 +81,26 @@ def test_cell_tensors_and_correction_properties():
     assert np.all(u[L.dirichlet_mask()] == 0)
     assert np.allclose(ln.correction(L, Ws, 2.5 * r), 2.5 * u, rtol=1e-12, atol=1e-14)
     assert np.all(ln.correction(L, Ws, np.zeros(L.ndofs)) == 0)
+
+
+def test_correction_through_next_level_properties():
+    """P net(P^T r): zero for r = 0, positively homogeneous, zero on the
+    fine level's Dirichlet rows, and equal to the plain correction when P is
+    the identity (the same level)."""
+    from oracle import learned as ln
+    from oracle.mg import Multigrid
+    import scipy.sparse as sp
+    mg = Multigrid(3, 2, 2, 1, 2, 0.05, nu=1.0, amp=0.03, n_coarse=1, k_min=1, omega=0.8)
+    Lf, Lc, P = mg.levels[0], mg.levels[1], mg.P[0]
+    assert (Lc.sp.r, Lc.k) == (1, 1)
+    Ws = ln.init_weights(4)
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal(Lf.ndofs)
+    r[Lf.dirichlet_mask()] = 0.0
+    assert np.all(ln.correction_through(Lc, P, Ws, 0 * r) == 0.0)
+    u = ln.correction_through(Lc, P, Ws, r)
+    assert np.allclose(ln.correction_through(Lc, P, Ws, 3.0 * r), 3.0 * u, rtol=1e-12, atol=0)
+    assert np.all(u[Lf.dirichlet_mask()] == 0.0)
+    rc = rng.standard_normal(Lc.ndofs)
+    I = sp.identity(Lc.ndofs, format="csr")
+    assert np.allclose(ln.correction_through(Lc, I, Ws, rc), ln.correction(Lc, Ws, rc), rtol=0, atol=1e-14)
