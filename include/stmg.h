@@ -70,8 +70,8 @@ typedef void (*stmg_nu_fn)(int npts, const double* xyz, double* nu_out, void* us
 
 typedef struct {
   int dim;               /* 2 or 3 */
-  int n_cells_1d;        /* fine mesh: n^d cells on [0,1]^d, n a power of two */
-  int n_coarse_1d;       /* cells per direction of the coarsest h-level */
+  int n_cells_1d;        /* fine mesh: n^d cells on [0,1]^d, n = n_coarse_1d 2^j */
+  int n_coarse_1d;       /* cells per direction of the coarsest h-level (>= 1) */
   double deform_amp;     /* vertices x_i += amp * prod_j sin(2 pi x_j) */
   int r, k;              /* velocity Q_{r+1}, pressure P_r^disc, DG(k) */
   int n_sub;             /* N subintervals of the slab */

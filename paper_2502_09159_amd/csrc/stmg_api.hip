@@ -545,8 +545,9 @@ stmg_status stmg_default_params(stmg_params* p) {
 static int check_params(const stmg_params* p, std::string& msg) {
   if (!p) { msg = "null params"; return STMG_EINVAL; }
   if (p->dim != 2 && p->dim != 3) { msg = "dim must be 2 or 3"; return STMG_EINVAL; }
-  if (!valid_pow2(p->n_cells_1d) || !valid_pow2(p->n_coarse_1d) || p->n_coarse_1d > p->n_cells_1d) {
-    msg = "n_cells_1d and n_coarse_1d must be powers of two with n_coarse_1d <= n_cells_1d"; return STMG_EINVAL;
+  if (p->n_coarse_1d < 1 || p->n_cells_1d < p->n_coarse_1d || p->n_cells_1d % p->n_coarse_1d != 0 ||
+      !valid_pow2(p->n_cells_1d / p->n_coarse_1d)) {
+    msg = "n_cells_1d must be n_coarse_1d times a power of two"; return STMG_EINVAL;
   }
   if (!valid_pow2(p->n_sub) || p->n_sub > 8) { msg = "n_sub must be 1, 2, 4 or 8"; return STMG_EINVAL; }
   if (p->r < 1 || p->r > 2 || p->r_min < 1 || p->r_min > p->r) { msg = "supported: 1 <= r_min <= r <= 2"; return STMG_EUNSUPPORTED; }

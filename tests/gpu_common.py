@@ -25,6 +25,10 @@ CONFIGS = {
                          placement=1),
     # 2D Q3/P2 x DG(2) on 8x8
     "2d_r2k2": dict(dim=2, n_cells_1d=8, n_coarse_1d=1, r=2, k=2, n_sub=2, deform_amp=0.03, k_min=1),
+    # ragged sizes: 6^3 cells (216: no multiple of a block or tile), a 3^3 coarse mesh, one subinterval
+    "ragged_n6_N1": dict(dim=3, n_cells_1d=6, n_coarse_1d=3, r=1, k=1, n_sub=1, deform_amp=0.03, k_min=1),
+    # DG(0) on the finest level (one temporal dof), Q3/P2 in space, 6^3 -> 3^3
+    "k0_n6": dict(dim=3, n_cells_1d=6, n_coarse_1d=3, r=2, k=0, n_sub=2, deform_amp=0.03, k_min=0),
 }
 TAU = 0.05
 OMEGA = 0.8

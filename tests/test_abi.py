@@ -56,7 +56,9 @@ def test_hierarchy_matches_oracle_rule():
              dict(dim=3, n_cells_1d=16, n_coarse_1d=2, r=2, k=2, n_sub=4, k_min=0, placement=1),
              dict(dim=3, n_cells_1d=16, n_coarse_1d=2, r=2, k=2, n_sub=4, k_min=0, placement=1,
                   time_h_coarsening=1),
-             dict(dim=3, n_cells_1d=32, n_coarse_1d=2, r=2, k=1, n_sub=8, time_h_coarsening=1)]
+             dict(dim=3, n_cells_1d=32, n_coarse_1d=2, r=2, k=1, n_sub=8, time_h_coarsening=1),
+             dict(dim=3, n_cells_1d=6, n_coarse_1d=3, r=1, k=1, n_sub=1),
+             dict(dim=3, n_cells_1d=12, n_coarse_1d=3, r=2, k=0, n_sub=2, k_min=0)]
     for c in cases:
         got = stmg.hierarchy(**c)
         ref = build_levels(c["n_cells_1d"], c["r"], c["k"], c["n_sub"], c["n_coarse_1d"], c.get("r_min", 1),
@@ -70,7 +72,9 @@ def test_invalid_parameters_are_rejected():
     with pytest.raises(stmg.StmgError):
         stmg.hierarchy(dim=4)
     with pytest.raises(stmg.StmgError):
-        stmg.hierarchy(n_cells_1d=6)
+        stmg.hierarchy(n_cells_1d=6)                  # 6 = 2 * 3: not n_coarse_1d (2) times a power of two
+    with pytest.raises(stmg.StmgError):
+        stmg.hierarchy(n_cells_1d=4, n_coarse_1d=8)
     with pytest.raises(stmg.StmgError):
         stmg.hierarchy(r=3)
     with pytest.raises(stmg.StmgError):

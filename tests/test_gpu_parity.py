@@ -192,3 +192,15 @@ def test_pressure_projection():
     xg = dev(x)
     g.project_pressure(xg)
     assert rel(host(xg), L.project_pressure(x)) < 1e-12
+
+
+def test_zero_right_hand_side():
+    """b = 0: no iteration, x = 0, relative residual 0."""
+    from paper_2502_09159_amd import stmg
+    g = solver("c5_small")
+    b = torch.zeros(g.ndofs(0), dtype=torch.float64, device="cuda")
+    x = torch.full_like(b, 7.0)
+    info = g.solve(b, x, rtol=1e-8)
+    announce(f"zero rhs: {info['iterations']} iterations")
+    assert info["iterations"] == 0
+    assert torch.count_nonzero(x).item() == 0
