@@ -8,6 +8,8 @@
 
 #include "kernels.hpp"
 
+#include <algorithm>
+
 namespace stmg {
 
 namespace {
@@ -1046,6 +1048,178 @@ __global__ __launch_bounds__(256) void k_vpass(const T* __restrict__ in, ArrLayo
   }
 }
 
+// Fused 3D velocity transfer: out_b (+)= (M x M x M) in_b for every field b,
+// with M (nout x nin) banded as in k_vpass.  One work group per output brick
+// BX x BY x BZ of one field: the input brick it needs (the union of the
+// rows' tap ranges along every axis, e0 x e1 x e2 nodes, listed per brick
+// by vtransfer_plan) is staged in LDS once, the x, y and z contractions run
+// in LDS, and the output is written (or accumulated, S::ACC) once.  LDS is dynamic,
+// sized by the host for the largest brick extents (VtBrick::lds_elems); a
+// block lays its arrays out with its own extents.  Every contraction reads
+// MAXT taps from its row's first tap on, unclamped: taps past the row carry
+// zero coefficients and land on finite values (the next row, or a zeroed
+// tail of MAXT - 1 rows behind each array).  The input boundary is zeroed on
+// load (mask_in), the output boundary on store (mask_out).
+template <int BX_, int BY_, int BZ_, bool ACC_>
+struct VtBrick {
+  static constexpr int BX = BX_, BY = BY_, BZ = BZ_;
+  static constexpr bool ACC = ACC_;  // accumulate into the output (prolongation) or overwrite it
+  // [s1: staged input + tail | y-pass output + tail] [s2: x-pass output + tail]
+  static size_t s1_elems(const int* e, int maxt) {
+    const size_t in = (size_t)e[0] * e[1] * e[2] + maxt, ypass = (size_t)(e[2] + maxt) * BY * BX;
+    return in > ypass ? in : ypass;
+  }
+  static size_t lds_elems(const int* cap, int maxt) {
+    return s1_elems(cap, maxt) + (size_t)(cap[2] * cap[1] + maxt) * BX;
+  }
+};
+using VtProlong = VtBrick<32, 8, 8, true>;     // fine output, coarse input
+using VtRestrict = VtBrick<16, 8, 4, false>;   // coarse output, fine input
+using VtRestrictS = VtBrick<8, 8, 4, false>;   // the same with narrower bricks (h-coarsening: wider tap ranges)
+
+// Launch geometry of k_vtransfer with the divisors it decodes block indices
+// by, each with its multiplier ceil(2^32 / d) (udiv_m).  Fields b = (n, a,
+// comp) of both sides are level-vector blocks (3 components, nt temporal dofs).
+struct VtGrid {
+  unsigned nbrick, m_nbrick, nbx, m_nbx, nbxy, m_nbxy, nt, m_nt;
+  int64_t slab_in, mv_in, nodes_in, slab_out, mv_out, nodes_out;
+};
+// floor(v / d) for v < 2^32 / d, m = ceil(2^32 / d) (d >= 2), d = 1 passed as m = 0
+__device__ __forceinline__ unsigned udiv_m(unsigned v, unsigned m) { return m ? __umulhi(v, m) : v; }
+
+template <typename T, int MAXT, typename S>
+__global__ __launch_bounds__(256) void k_vtransfer(const T* __restrict__ in, T* __restrict__ out, VtGrid G,
+                                                   int nin, int nout, const T* __restrict__ M,
+                                                   const int* __restrict__ tlo, int mask_in, int mask_out,
+                                                   const int* __restrict__ brk) {
+  constexpr int BX = S::BX, BY = S::BY, BZ = S::BZ, NOUT = BZ * BY * BX, OT = (NOUT + 255) / 256;
+  constexpr int RX = 256 / BX, RZ = 256 / (BX * BY);  // rows per sweep of the x pass, z planes per sweep
+  static_assert(256 % BX == 0 && 256 % (BX * BY) == 0, "brick shape");
+  extern __shared__ __align__(16) unsigned char vt_raw[];
+  const int tid = threadIdx.x;
+  const unsigned lb = (unsigned)xcd_remap(blockIdx.x + (int64_t)gridDim.x * blockIdx.y,
+                                          (int64_t)gridDim.x * gridDim.y);
+  const unsigned field = udiv_m(lb, G.m_nbrick), brick = lb - field * G.nbrick;
+  const unsigned kz = udiv_m(brick, G.m_nbxy), rxy = brick - kz * G.nbxy, ky = udiv_m(rxy, G.m_nbx);
+  const int nbx = (int)G.nbx, nby = (int)(G.nbxy / G.nbx);
+  const int kb[3] = {(int)(rxy - ky * G.nbx), (int)ky, (int)kz};
+  const int o0[3] = {kb[0] * BX, kb[1] * BY, kb[2] * BZ};
+  const unsigned ft = field / 3u, comp = field - 3u * ft, fn = udiv_m(ft, G.m_nt), fa = ft - fn * G.nt;
+  const int on[3] = {min(BX, nout - o0[0]), min(BY, nout - o0[1]), min(BZ, nout - o0[2])};
+  // staged input range of this brick along every axis
+  const int i0[3] = {brk[2 * kb[0]], brk[2 * (nbx + kb[1])], brk[2 * (nbx + nby + kb[2])]};
+  const int ext[3] = {brk[2 * kb[0] + 1], brk[2 * (nbx + kb[1]) + 1], brk[2 * (nbx + nby + kb[2]) + 1]};
+  T* dst = out + (int64_t)fn * G.slab_out + (int64_t)fa * G.mv_out + (int64_t)comp * G.nodes_out;
+  // this thread's x and y output positions (fixed for the whole block), their
+  // coefficients and first taps relative to the staged range
+  const int ox = tid % BX, oy = (tid / BX) % BY;
+  const int gxo = o0[0] + min(ox, on[0] - 1), gyo = o0[1] + min(oy, on[1] - 1);
+  T cx[MAXT], cy[MAXT];
+#pragma unroll
+  for (int u = 0; u < MAXT; ++u) {
+    cx[u] = M[u * nout + gxo];
+    cy[u] = M[u * nout + gyo];
+  }
+  const int offx = max(tlo[gxo] - i0[0], 0), offy = max(tlo[gyo] - i0[1], 0);
+  // outputs of this thread, and (accumulating) their old values, fetched now
+  int64_t gout[OT];
+  T prev[OT];
+#pragma unroll
+  for (int e = 0; e < OT; ++e) {
+    const int oz = min(tid / (BX * BY) + RZ * e, on[2] - 1);
+    gout[e] = ((int64_t)(o0[2] + oz) * nout + gyo) * nout + gxo;
+    prev[e] = S::ACC ? dst[gout[e]] : T(0);
+  }
+  T* s1 = reinterpret_cast<T*>(vt_raw);
+  const int n1 = max(ext[0] * ext[1] * ext[2] + MAXT, (ext[2] + MAXT) * BY * BX);
+  T* s2 = s1 + n1;
+  const T* src = in + (int64_t)fn * G.slab_in + (int64_t)fa * G.mv_in + (int64_t)comp * G.nodes_in;
+  // ---- stage the input brick: RW lanes per row (RW = 32 or 64), 256 / RW
+  // rows of one z-plane per sweep; the sweeps (z, j) are walked uniformly,
+  // CH at a time.  Offsets inside the field are 32-bit; rows past the
+  // brick are read from its last row (in bounds) and not stored.
+  {
+    const int lrw = ext[0] <= 32 ? 5 : 6, rs = 256 >> lrw;
+    const int ix = tid & ((1 << lrw) - 1), iyl = tid >> lrw;
+    const int gx = i0[0] + min(ix, ext[0] - 1);
+    const bool xin = ix < ext[0];
+    const bool xb = (mask_in != 0) & ((gx == 0) | (gx == nin - 1));
+    const int nsw = (ext[1] + rs - 1) / rs, nq = ext[2] * nsw, plane = nin * nin;
+    constexpr int CH = 8;
+    int iz = 0, jj = 0;  // sweep q0 = (iz, jj)
+    for (int q0 = 0; q0 < nq; q0 += CH) {
+      T v[CH];
+      bool keep[CH];
+      int z = iz, j = jj;
+#pragma unroll
+      for (int e = 0; e < CH; ++e) {
+        const int gy = i0[1] + min(j * rs + iyl, ext[1] - 1), gz = i0[2] + min(z, ext[2] - 1);
+        const bool zb = (gz == 0) | (gz == nin - 1), yb = (gy == 0) | (gy == nin - 1);
+        keep[e] = !(xb | ((mask_in != 0) & (yb | zb)));
+        v[e] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(src) +
+                                           (unsigned)(gz * plane + gy * nin + gx) * (unsigned)sizeof(T));
+        if (++j == nsw) {
+          j = 0;
+          ++z;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < CH; ++e) {
+        const int iy = jj * rs + iyl;
+        if ((q0 + e < nq) & xin & (iy < ext[1])) s1[(iz * ext[1] + iy) * ext[0] + ix] = keep[e] ? v[e] : T(0);
+        if (++jj == nsw) {
+          jj = 0;
+          ++iz;
+        }
+      }
+    }
+    if (tid < MAXT) s1[ext[0] * ext[1] * ext[2] + tid] = T(0);
+  }
+  __syncthreads();
+  // ---- x: s2[row][ox], row = (iz, iy)
+  {
+    const int nrow = ext[1] * ext[2];
+    if (ox < on[0])
+      for (int row = tid / BX; row < nrow; row += RX) {
+        const T* p = s1 + row * ext[0] + offx;
+        T sum = 0;
+#pragma unroll
+        for (int u = 0; u < MAXT; ++u) sum += cx[u] * p[u];
+        s2[row * BX + ox] = sum;
+      }
+    if (tid < MAXT * BX) s2[nrow * BX + tid] = T(0);
+  }
+  __syncthreads();
+  // ---- y: s1[iz][oy][ox]
+  {
+    if (ox < on[0] && oy < on[1])
+      for (int iz = tid / (BX * BY); iz < ext[2]; iz += RZ) {
+        const T* p = s2 + (iz * ext[1] + offy) * BX + ox;
+        T sum = 0;
+#pragma unroll
+        for (int u = 0; u < MAXT; ++u) sum += cy[u] * p[u * BX];
+        s1[(iz * BY + oy) * BX + ox] = sum;
+      }
+    for (int t = tid; t < MAXT * BY * BX; t += 256) s1[ext[2] * BY * BX + t] = T(0);
+  }
+  __syncthreads();
+  // ---- z, then the output brick (the z position is uniform over a wave)
+#pragma unroll
+  for (int e = 0; e < OT; ++e) {
+    const int oz = __builtin_amdgcn_readfirstlane(tid / (BX * BY) + RZ * e);
+    if (oz < on[2] && ox < on[0] && oy < on[1]) {
+      const int gz = o0[2] + oz, offz = max(tlo[gz] - i0[2], 0);
+      const T* p = s1 + (offz * BY + oy) * BX + ox;
+      T sum = 0;
+#pragma unroll
+      for (int u = 0; u < MAXT; ++u) sum += M[u * nout + gz] * p[u * BY * BX];
+      if (mask_out && (gxo == 0 || gxo == nout - 1 || gyo == 0 || gyo == nout - 1 || gz == 0 || gz == nout - 1))
+        sum = 0;
+      dst[gout[e]] = S::ACC ? prev[e] + sum : sum;
+    }
+  }
+}
+
 // Pressure: prolong (dir 0): xf[cf][l] += sum_m E[pos][l][m] xc[parent][m];
 // restrict (dir 1): bc[cp][m] = sum_children sum_l E[pos][l][m] rf[child][l].
 template <typename T>
@@ -1118,16 +1292,105 @@ __global__ void k_tpass(const T* __restrict__ in, T* __restrict__ out, int ns_in
 
 static inline unsigned nblk(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
+
+// taps per contraction of the fused transfer kernel (its MAXT) for rows of up
+// to max_row taps
+static int vt_taps(int max_row) { return max_row <= 3 ? 3 : (max_row <= 5 ? 5 : (max_row <= 7 ? 7 : 8)); }
+
+// staged input range (first node, extent) of every output brick of `b` rows
+// along one axis, appended to `out`; returns the largest extent
+static int brick_ranges(const std::vector<int>& lo, const std::vector<int>& hi, int b, std::vector<int>& out) {
+  const int nout = (int)lo.size();
+  int worst = 1;
+  for (int o0 = 0; o0 < nout; o0 += b) {
+    int a = 0x7fffffff, e = -1;
+    for (int o = o0; o < std::min(o0 + b, nout); ++o)
+      if (hi[o] > lo[o]) {
+        a = std::min(a, lo[o]);
+        e = std::max(e, hi[o]);
+      }
+    if (e <= a) {  // no tap in the brick
+      a = 0;
+      e = 1;
+    }
+    out.push_back(a);
+    out.push_back(e - a);
+    worst = std::max(worst, e - a);
+  }
+  return worst;
+}
+
+template <typename S>
+static size_t vt_plan_bytes(const std::vector<int>& lo, const std::vector<int>& hi, int max_row, size_t elem,
+                            int* cap, std::vector<int>& brk) {
+  brk.clear();
+  cap[0] = brick_ranges(lo, hi, S::BX, brk);
+  cap[1] = brick_ranges(lo, hi, S::BY, brk);
+  cap[2] = brick_ranges(lo, hi, S::BZ, brk);
+  if (cap[0] > 64 || cap[1] > 64 || cap[2] > 64) return ~(size_t)0;
+  return S::lds_elems(cap, vt_taps(max_row)) * elem;
+}
+
+int vtransfer_plan(const std::vector<int>& lo, const std::vector<int>& hi, int d, int max_row, bool restriction,
+                   size_t elem, int* cap, std::vector<int>& brk) {
+  if (d != 3 || max_row > 8) return 0;
+  if (!restriction) return vt_plan_bytes<VtProlong>(lo, hi, max_row, elem, cap, brk) <= 48 * 1024 ? 1 : 0;
+  if (vt_plan_bytes<VtRestrict>(lo, hi, max_row, elem, cap, brk) <= 40 * 1024) return 2;
+  if (vt_plan_bytes<VtRestrictS>(lo, hi, max_row, elem, cap, brk) <= 56 * 1024) return 3;
+  return 0;
+}
+
+namespace {
+unsigned udiv_mult(unsigned d) { return d <= 1 ? 0u : (unsigned)((0x100000000ULL + d - 1) / d); }
+
+template <typename T, typename S>
+void launch_vt(const T* in, ArrLayout li, T* out, ArrLayout lo, int nin, int nout, int64_t nb, int max_row,
+               const T* M, const int* tlo, int mask_in, int mask_out, const int* cap, const int* brk,
+               hipStream_t s) {
+  VtGrid G;
+  G.nbx = (unsigned)((nout + S::BX - 1) / S::BX);
+  G.nbxy = G.nbx * (unsigned)((nout + S::BY - 1) / S::BY);
+  G.nbrick = G.nbxy * (unsigned)((nout + S::BZ - 1) / S::BZ);
+  G.nt = (unsigned)li.nt;
+  G.m_nbrick = udiv_mult(G.nbrick);
+  G.m_nbx = udiv_mult(G.nbx);
+  G.m_nbxy = udiv_mult(G.nbxy);
+  G.m_nt = udiv_mult(G.nt);
+  G.slab_in = li.slab; G.mv_in = li.Mv; G.nodes_in = li.nodes;
+  G.slab_out = lo.slab; G.mv_out = lo.Mv; G.nodes_out = lo.nodes;
+  const dim3 grid(G.nbrick, (unsigned)nb);
+  const int taps = vt_taps(max_row);
+  const size_t bytes = S::lds_elems(cap, taps) * sizeof(T);
+  auto go = [&](auto kern) {
+    kern<<<grid, 256, bytes, s>>>(in, out, G, nin, nout, M, tlo, mask_in, mask_out, brk);
+  };
+  if (taps == 3) go(k_vtransfer<T, 3, S>);
+  else if (taps == 5) go(k_vtransfer<T, 5, S>);
+  else if (taps == 7) go(k_vtransfer<T, 7, S>);
+  else go(k_vtransfer<T, 8, S>);
+}
+}  // namespace
+
 template <typename T>
 static void space_velocity(const LevelArgs& Li, const LevelArgs& Lo, int nt, int N, const T* M, const int* lo,
-                           const int* hi, int max_row, const T* in, ArrLayout li, T* out, ArrLayout lout, T* tmp1,
-                           T* tmp2, bool restrict_, hipStream_t s) {
+                           const int* hi, int max_row, int brick, const int* cap, const int* brk, const T* in,
+                           ArrLayout li, T* out, ArrLayout lout, T* tmp1, T* tmp2, bool restrict_, hipStream_t s) {
   // Li: spatial sizes of the input, Lo: of the output.  Prolongation runs the
   // passes x, y, z and restriction z, y, x, so that the x pass (whose taps
   // differ from lane to lane) always works on the coarse side of the
   // intermediate arrays.
   const int d = Li.d;
   const int64_t nb = (int64_t)N * nt * d;
+  if (brick > 0 && d == 3 && li.level && lout.level && li.nt == lout.nt) {  // one fused launch
+    const int mi = 1, mo = restrict_ ? 1 : 0;  // prolongation accumulates (VtProlong::ACC)
+    if (brick == 1)
+      launch_vt<T, VtProlong>(in, li, out, lout, Li.nn, Lo.nn, nb, max_row, M, lo, mi, mo, cap, brk, s);
+    else if (brick == 2)
+      launch_vt<T, VtRestrict>(in, li, out, lout, Li.nn, Lo.nn, nb, max_row, M, lo, mi, mo, cap, brk, s);
+    else
+      launch_vt<T, VtRestrictS>(in, li, out, lout, Li.nn, Lo.nn, nb, max_row, M, lo, mi, mo, cap, brk, s);
+    return;
+  }
   int dims[3] = {Li.nn, Li.nn, d == 3 ? Li.nn : 1};
   const T* src = in;
   ArrLayout ls = li;
@@ -1177,7 +1440,8 @@ hipError_t launch_prolongate_add(const LevelArgs& F, const LevelArgs& Cs, const 
   }
   ArrLayout li{1, nt_src, F.d, slab_src, Cs.Mv, Cs.nodes, 0};
   ArrLayout lo{1, F.nt, F.d, F.slab, F.Mv, F.nodes, 0};
-  space_velocity<T>(Cs, F, F.nt, F.N, P1, rlo, rhi, t.max_row_p1, src, li, xf, lo, tmp1, tmp2, false, s);
+  space_velocity<T>(Cs, F, F.nt, F.N, P1, rlo, rhi, t.max_row_p1, t.vt_p1, t.cap_p1, t.brk_p1, src, li, xf, lo,
+                    tmp1, tmp2, false, s);
   int64_t tot = (int64_t)F.N * F.nt * (int64_t)(F.Mp);
   k_ppass<T><<<nblk(tot), 256, 0, s>>>(src, xf, F.N * F.nt, nt_src, F.nt, slab_src, (int64_t)nt_src * Cs.Mv, Cs.Mp,
                                        F.slab, (int64_t)F.nt * F.Mv, F.Mp, F.d, F.n, Cs.n, F.C, Cs.C, E, t.npos, 0,
@@ -1193,7 +1457,8 @@ hipError_t launch_restrict(const LevelArgs& F, const LevelArgs& Cs, const Transf
   int64_t slab_dst = t.time_change ? (int64_t)F.nt * (Cs.Mv + Cs.Mp) : Cs.slab;
   ArrLayout li{1, F.nt, F.d, F.slab, F.Mv, F.nodes, 0};
   ArrLayout lo{1, F.nt, F.d, slab_dst, Cs.Mv, Cs.nodes, 0};
-  space_velocity<T>(F, Cs, F.nt, F.N, P1T, clo, chi, t.max_row_p1t, rf, li, dst, lo, tmp1, tmp2, true, s);
+  space_velocity<T>(F, Cs, F.nt, F.N, P1T, clo, chi, t.max_row_p1t, t.vt_p1t, t.cap_p1t, t.brk_p1t, rf, li, dst,
+                    lo, tmp1, tmp2, true, s);
   int64_t ncc = 1;
   for (int j = 0; j < F.d; ++j) ncc *= Cs.n;
   int64_t tot = (int64_t)F.N * F.nt * ncc * Cs.C;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace stmg {
 
@@ -71,7 +72,19 @@ struct TransferDev {
   int nnf, nnc, npos, ntf, ntc;
   bool time_change;
   int max_row_p1, max_row_p1t;  // longest nonzero range of a row of P1 / P1T
+  int vt_p1 = 0, vt_p1t = 0;  // brick of the fused 3D prolongation / restriction (0: one pass per axis)
+  int cap_p1[3] = {0, 0, 0}, cap_p1t[3] = {0, 0, 0};  // their largest staged brick extents
+  const int* brk_p1 = nullptr;   // device: staged range (first, extent) of every brick, axis by axis
+  const int* brk_p1t = nullptr;
 };
+// Plan of the fused 3D velocity transfer for the banded 1D matrix with row
+// ranges [lo[o], hi[o]) and elements of `elem` bytes: picks the output brick
+// whose staged input fits the LDS budget and returns its id (0 if none does:
+// then the transfer runs as one pass per axis).  cap: largest staged extent
+// per axis; brk: (first input node, extent) of every brick along x, then y,
+// then z (bricks of the axis' own size).
+int vtransfer_plan(const std::vector<int>& lo, const std::vector<int>& hi, int d, int max_row, bool restriction,
+                   size_t elem, int* cap, std::vector<int>& brk);
 template <typename T>
 hipError_t launch_prolongate_add(const LevelArgs& F, const LevelArgs& Cs, const TransferDev& t,
                                  const T* P1, const int* rlo, const int* rhi, const T* E, const T* Pt,

@@ -243,6 +243,11 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
     for (int h = 0; h < T0.nnc; ++h) X.t.max_row_p1t = std::max(X.t.max_row_p1t, T0.col_hi[h] - T0.col_lo[h]);
     if (X.t.max_row_p1 > 16 || X.t.max_row_p1t > 16)
       throw Error(STMG_EUNSUPPORTED, "transfer rows longer than 16 taps");
+    std::vector<int> brk;
+    X.t.vt_p1 = vtransfer_plan(T0.row_lo, T0.row_hi, F.d, X.t.max_row_p1, false, sizeof(T), X.t.cap_p1, brk);
+    if (X.t.vt_p1) X.t.brk_p1 = c->pool.upload<int>(brk, s);
+    X.t.vt_p1t = vtransfer_plan(T0.col_lo, T0.col_hi, F.d, X.t.max_row_p1t, true, sizeof(T), X.t.cap_p1t, brk);
+    if (X.t.vt_p1t) X.t.brk_p1t = c->pool.upload<int>(brk, s);
     // banded, transposed: Mb[u][row] = M[row][lo(row) + u], u < 16 (zero past the row)
     std::vector<double> P1b((size_t)16 * T0.nnf, 0.0), P1Tb((size_t)16 * T0.nnc, 0.0);
     for (int g = 0; g < T0.nnf; ++g)

@@ -24,7 +24,8 @@ def per_kernel(path, counter):
                       (counter,)).fetchall()
     agg = {}
     for name, grid, val in rows:
-        k = (name.split("(")[0].replace("void ", "").replace("stmg::", ""), grid)
+        k = (name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").replace("stmg::", ""),
+             grid)
         a = agg.setdefault(k, [0, 0.0])
         a[0] += 1
         a[1] += val
