@@ -417,6 +417,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
 // ceil(nn / rows) nn (3D) or ceil(nn / rows) (2D), d nt N fields).
 //   KIND 0 (operator): y = sum (mode 0) or b - sum (mode 1); Dirichlet rows identity
 //   KIND 1 (smoother): x += omega / valence * sum; Dirichlet nodes unchanged
+//                      (mode 1: x starts at 0, so x = omega / valence * sum and 0)
 template <typename T, int D, int QQ, int KIND>
 __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __restrict__ E, const T* __restrict__ xin,
                                                      const T* __restrict__ b, T* __restrict__ out, int mode,
@@ -437,12 +438,13 @@ __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __res
   const int g0 = q * c;
   const bool last = c == L.n - 1;
   if (brow) {  // every node of a boundary row is a Dirichlet node
-    if (KIND == 0) {
+    if (KIND == 0 || mode) {
 #pragma unroll
       for (int j = 0; j < q + 1; ++j) {
         if (j == q && !last) break;
         const int64_t id = row0 + g0 + j;
-        out[id] = mode ? b[id] - xin[id] : xin[id];
+        if (KIND == 0) out[id] = mode ? b[id] - xin[id] : xin[id];
+        else out[id] = T(0);
       }
     }
     return;
@@ -492,7 +494,9 @@ __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __res
       else out[id] = mode ? b[id] - sj : sj;
     } else if (!dir) {
       const T val = (j == 0 && c > 0) ? vyz * T(2) : vyz;
-      out[id] += omega / val * sj;
+      out[id] = mode ? omega / val * sj : out[id] + omega / val * sj;
+    } else if (mode) {
+      out[id] = T(0);
     }
   }
 }
@@ -592,7 +596,7 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
                                                     const T* __restrict__ Bm, const T* __restrict__ F,
                                                     const T* __restrict__ Hinv, const T* __restrict__ coef,
                                                     const T* __restrict__ r, T* __restrict__ x, T omega,
-                                                    T* __restrict__ E) {
+                                                    T* __restrict__ E, int xzero) {
   constexpr int NL = D == 3 ? Q * Q * Q : Q * Q;
   constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
   constexpr int M = NT * NL, MP = (M + 15) / 16 * 16, NKB = MP / 16, P = NT * C;
@@ -777,7 +781,7 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
 #pragma unroll
       for (int q = 0; q < P; ++q) s += hv[j][q] * S[q * N + n];
       YP[pp * N + n] = s;
-      x[pidx(L, n, pp / C, cell, pp % C)] = xp[j] + omega * s;
+      x[pidx(L, n, pp / C, cell, pp % C)] = (xzero ? T(0) : xp[j]) + omega * s;  // xzero: x starts at 0
     }
   }
   __syncthreads();
@@ -805,13 +809,14 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
 }
 
 template <typename T>
-static hipError_t vanka_gather(const LevelArgs& L, const T* E, T* x, T omega, hipStream_t s) {
-  return node_gather<T, 1>(L, E, nullptr, nullptr, x, 0, omega, s);
+static hipError_t vanka_gather(const LevelArgs& L, const T* E, T* x, T omega, hipStream_t s, bool xzero = false) {
+  return node_gather<T, 1>(L, E, nullptr, nullptr, x, xzero ? 1 : 0, omega, s);
 }
 
 template <typename T, int D, int Q, int NT>
 static hipError_t vanka_fact_impl(const LevelArgs& L, const T* Asw, const T* Bm, const T* F, const T* Hinv,
-                                  const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s, bool gather) {
+                                  const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s, bool gather,
+                                  bool xzero) {
   constexpr int NL = D == 3 ? Q * Q * Q : Q * Q;
   constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
   constexpr int M = NT * NL, MP = (M + 15) / 16 * 16, P = NT * C;
@@ -825,7 +830,7 @@ static hipError_t vanka_fact_impl(const LevelArgs& L, const T* Asw, const T* Bm,
       hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
       if (e != hipSuccess) return e;
     }
-    kern<<<(unsigned)ncells, 256, bytes, s>>>(L, Asw, Bm, F, Hinv, coef, r, x, omega, E);
+    kern<<<(unsigned)ncells, 256, bytes, s>>>(L, Asw, Bm, F, Hinv, coef, r, x, omega, E, xzero ? 1 : 0);
     return hipSuccess;
   };
   hipError_t e;
@@ -838,7 +843,7 @@ static hipError_t vanka_fact_impl(const LevelArgs& L, const T* Asw, const T* Bm,
   }
   if (e != hipSuccess) return e;
   if (!gather) return hipGetLastError();
-  return vanka_gather<T>(L, E, x, omega, s);
+  return vanka_gather<T>(L, E, x, omega, s, xzero);
 }
 
 template <typename T>
@@ -848,9 +853,11 @@ hipError_t launch_vanka_gather_only(const LevelArgs& L, const T* E, T* x, T omeg
 
 template <typename T>
 hipError_t launch_vanka_factored(const LevelArgs& L, const T* Asw, const T* Bm, const T* F, const T* Hinv,
-                                 const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s, bool gather) {
-#define STMG_VF(DD, QQ, KK) \
-  if (L.d == DD && L.Q == QQ && L.nt == KK) return vanka_fact_impl<T, DD, QQ, KK>(L, Asw, Bm, F, Hinv, coef, r, x, omega, E, s, gather);
+                                 const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s, bool gather,
+                                 bool xzero) {
+#define STMG_VF(DD, QQ, KK)                                                                                   \
+  if (L.d == DD && L.Q == QQ && L.nt == KK)                                                                   \
+    return vanka_fact_impl<T, DD, QQ, KK>(L, Asw, Bm, F, Hinv, coef, r, x, omega, E, s, gather, xzero);
   STMG_VF(2, 3, 1) STMG_VF(2, 3, 2) STMG_VF(2, 3, 3) STMG_VF(2, 3, 4)
   STMG_VF(2, 4, 1) STMG_VF(2, 4, 2) STMG_VF(2, 4, 3) STMG_VF(2, 4, 4)
   STMG_VF(3, 3, 1) STMG_VF(3, 3, 2) STMG_VF(3, 3, 3) STMG_VF(3, 3, 4)
@@ -1628,6 +1635,13 @@ __device__ __forceinline__ void block_sums_out(const double (&acc)[NA], int nv, 
   }
 }
 
+// Both passes read NVM basis vectors per element unconditionally, in
+// chunks of up to 16 whose loads are all in flight together: vector k >=
+// (number in use) is read from the last one in use (an L1/L2 hit) and
+// weighted by zero (predicated loads would each be followed by a full wait).
+// NVM runs in steps of 4 up to 32, so at most 3 such reads per element.
+constexpr int kCgsChunk = 16;
+
 // First pass of a step with j final basis vectors V_0..V_{j-1} and a pending
 // vector u with second-projection coefficients h2 and norm 1/invb:
 //   V_j = (u - sum_{k<j} h2_k V_k) invb   (written; skipped when pending == 0)
@@ -1637,62 +1651,74 @@ __global__ __launch_bounds__(256) void k_lcgs_a(double* __restrict__ V, int64_t 
                                                 const double* __restrict__ u, const double* __restrict__ h2,
                                                 double invb, const double* __restrict__ w, int64_t n,
                                                 double* __restrict__ partial) {
-  constexpr bool KEEP = NVM <= 32;
   __shared__ double sh[NVM * 4];
+  const int nf = pending ? j : j + 1;  // final vectors read (>= 1)
   double acc[NVM];
 #pragma unroll
   for (int k = 0; k < NVM; ++k) acc[k] = 0.0;
-  const int nf = pending ? j : j + 1;  // final vectors read
   double* vj = V + (int64_t)j * ldv;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double vv[KEEP ? NVM : 1];
     const double wi = w[i];
+    const double ui = pending ? u[i] : 0.0;
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < NVM; ++k)
-      if (k < nf) {
-        const double vk = V[(int64_t)k * ldv + i];
-        if constexpr (KEEP) vv[k] = vk;
-        if (pending) s += h2[k] * vk;
-        acc[k] += vk * wi;
+    for (int c = 0; c < NVM; c += kCgsChunk) {
+      constexpr int CN = NVM < kCgsChunk ? NVM : kCgsChunk;
+      double v[CN];
+#pragma unroll
+      for (int k = 0; k < CN; ++k) v[k] = V[(int64_t)min(c + k, nf - 1) * ldv + i];
+#pragma unroll
+      for (int k = 0; k < CN; ++k) {
+        const bool in = c + k < nf;
+        s += (pending && in ? h2[c + k] : 0.0) * v[k];
+        acc[c + k] += (in ? 1.0 : 0.0) * (v[k] * wi);
       }
+    }
     if (pending) {
-      const double vn = (u[i] - s) * invb;
+      const double vn = (ui - s) * invb;
       vj[i] = vn;
 #pragma unroll
-      for (int k = 0; k < NVM; ++k)
-        if (k == j) acc[k] += vn * wi;
+      for (int k = 0; k < NVM; ++k) acc[k] += (k == j ? 1.0 : 0.0) * (vn * wi);
     }
   }
   block_sums_out<NVM>(acc, j + 1, sh, partial);
 }
 
 // Second pass: w -= sum_{k<nv} h_k V_k, then partial sums of V_k . w (updated
-// w) for k < nv and of w . w (index nv).
+// w) for k < nv and of w . w (index nv).  The basis values stay in registers
+// up to 16 vectors; beyond, the second use reads them again (L2).
 template <int NVM>
 __global__ __launch_bounds__(256) void k_axpy_mdot(double* __restrict__ w, const double* __restrict__ V,
                                                    int64_t ldv, int nv, const double* __restrict__ h, int64_t n,
                                                    double* __restrict__ partial) {
-  constexpr bool KEEP = NVM <= 32;
+  constexpr bool KEEP = NVM <= kCgsChunk;
+  constexpr int CN = NVM < kCgsChunk ? NVM : kCgsChunk;
   __shared__ double sh[(NVM + 1) * 4];
   double acc[NVM + 1];
 #pragma unroll
   for (int k = 0; k <= NVM; ++k) acc[k] = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double vv[KEEP ? NVM : 1];
+    const double w0 = w[i];
+    double v[CN];
     double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < NVM; ++k)
-      if (k < nv) {
-        const double vk = V[(int64_t)k * ldv + i];
-        if constexpr (KEEP) vv[k] = vk;
-        s += h[k] * vk;
-      }
-    const double wi = w[i] - s;
+    for (int c = 0; c < NVM; c += kCgsChunk) {
+#pragma unroll
+      for (int k = 0; k < CN; ++k) v[k] = V[(int64_t)min(c + k, nv - 1) * ldv + i];
+#pragma unroll
+      for (int k = 0; k < CN; ++k) s += (c + k < nv ? h[c + k] : 0.0) * v[k];
+    }
+    const double wi = w0 - s;
     w[i] = wi;
 #pragma unroll
-    for (int k = 0; k < NVM; ++k)
-      if (k < nv) acc[k] += (KEEP ? vv[KEEP ? k : 0] : V[(int64_t)k * ldv + i]) * wi;
+    for (int c = 0; c < NVM; c += kCgsChunk) {
+      if constexpr (!KEEP) {
+#pragma unroll
+        for (int k = 0; k < CN; ++k) v[k] = V[(int64_t)min(c + k, nv - 1) * ldv + i];
+      }
+#pragma unroll
+      for (int k = 0; k < CN; ++k) acc[c + k] += (c + k < nv ? 1.0 : 0.0) * (v[k] * wi);
+    }
     acc[NVM] += wi * wi;
   }
   // move the norm next to the nv dot products
@@ -1702,12 +1728,26 @@ __global__ __launch_bounds__(256) void k_axpy_mdot(double* __restrict__ w, const
   block_sums_out<NVM + 1>(out, nv + 1, sh, partial);
 }
 
-__global__ void k_fused_final(const double* __restrict__ partial, int nv, double* __restrict__ out) {
-  const int vi = blockIdx.x * blockDim.x + threadIdx.x;
+// out[v] = sum of the kFusedBlocks partial sums of vector v: one 256-thread
+// block per vector, each thread a strided eighth of them, then a fixed tree
+// over the block (the order never changes, so results are reproducible).
+__global__ __launch_bounds__(256) void k_fused_final(const double* __restrict__ partial, int nv,
+                                                     double* __restrict__ out) {
+  static_assert(kFusedBlocks % 256 == 0, "partial layout");
+  __shared__ double sh[4];
+  const int vi = blockIdx.x;
   if (vi >= nv) return;
+  const double* p = partial + (int64_t)vi * kFusedBlocks + threadIdx.x;
+  double v[kFusedBlocks / 256];
+#pragma unroll
+  for (int k = 0; k < kFusedBlocks / 256; ++k) v[k] = p[256 * k];
   double s = 0.0;
-  for (int b = 0; b < kFusedBlocks; ++b) s += partial[(int64_t)vi * kFusedBlocks + b];
-  out[vi] = s;
+#pragma unroll
+  for (int k = 0; k < kFusedBlocks / 256; ++k) s += v[k];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[vi] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
 template <int NVM>
@@ -1716,9 +1756,9 @@ static void lcgs2_impl(double* V, int64_t ldv, int j, int pending, const double*
                        hipStream_t s) {
   const int nv = j + 1;
   k_lcgs_a<NVM><<<kFusedBlocks, 256, 0, s>>>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial);
-  k_fused_final<<<1, 64, 0, s>>>(partial, nv, h1);
+  k_fused_final<<<nv, 256, 0, s>>>(partial, nv, h1);
   k_axpy_mdot<NVM><<<kFusedBlocks, 256, 0, s>>>(w, V, ldv, nv, h1, n, partial);
-  k_fused_final<<<2, 64, 0, s>>>(partial, nv + 1, h2n);
+  k_fused_final<<<nv + 1, 256, 0, s>>>(partial, nv + 1, h2n);
 }
 
 hipError_t launch_lcgs2(double* V, int64_t ldv, int j, int pending, const double* u, const double* h2_prev,
@@ -1726,11 +1766,14 @@ hipError_t launch_lcgs2(double* V, int64_t ldv, int j, int pending, const double
                         hipStream_t s) {
   const int nv = j + 1;
   if (j < 0 || nv > kMaxFused || (!pending && j != 0)) return hipErrorInvalidValue;
-  if (nv <= 4) lcgs2_impl<4>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial, h1, h2n, s);
-  else if (nv <= 8) lcgs2_impl<8>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial, h1, h2n, s);
-  else if (nv <= 16) lcgs2_impl<16>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial, h1, h2n, s);
-  else if (nv <= 32) lcgs2_impl<32>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial, h1, h2n, s);
-  else lcgs2_impl<64>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial, h1, h2n, s);
+#define STMG_LC(K) \
+  if (nv <= K) {   \
+    lcgs2_impl<K>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial, h1, h2n, s); \
+    return hipGetLastError();                                                     \
+  }
+  STMG_LC(4) STMG_LC(8) STMG_LC(12) STMG_LC(16) STMG_LC(20) STMG_LC(24) STMG_LC(28) STMG_LC(32)
+  STMG_LC(40) STMG_LC(48) STMG_LC(56) STMG_LC(64)
+#undef STMG_LC
   return hipGetLastError();
 }
 
@@ -1796,7 +1839,7 @@ hipError_t launch_project_pressure(const LevelArgs& L, const double* mom, double
   template hipError_t launch_apply<T>(const LevelArgs&, const T*, const T*, const T*, const T*, T*, int, T*,      \
                                       hipStream_t, bool);                                                           \
   template hipError_t launch_vanka_factored<T>(const LevelArgs&, const T*, const T*, const T*, const T*, const T*, \
-                                               const T*, T*, T, T*, hipStream_t, bool);                             \
+                                               const T*, T*, T, T*, hipStream_t, bool, bool);                       \
   template hipError_t launch_vanka_dense<T>(const LevelArgs&, const T*, const T*, T*, T, hipStream_t);             \
   template hipError_t launch_prolongate_add<T>(const LevelArgs&, const LevelArgs&, const TransferDev&, const T*,   \
                                                const int*, const int*, const T*, const T*, const T*, T*, T*, T*,    \

@@ -47,9 +47,10 @@ hipError_t launch_apply(const LevelArgs& L, const T* geo, const T* tab, const T*
 // values (the velocity corrections, summed per node by a gather kernel).
 template <typename T>
 // gather = false runs the local solves only (E and the pressure updates): for timing.
+// xzero: x holds no values yet and is taken as 0 (it is overwritten, not updated).
 hipError_t launch_vanka_factored(const LevelArgs& L, const T* Asw, const T* Bm, const T* F, const T* Hinv,
                                  const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s,
-                                 bool gather = true);
+                                 bool gather = true, bool xzero = false);
 // Position of A_s^{-1}[row][k] inside one cell's swizzled block (mp x mp):
 // row tile t = row/16, k chunk kb = k/16, lane = row%16 + 16*((k%16)/4), slot k%4.
 inline int64_t vanka_swizzle_index(int mp, int row, int k) {

@@ -282,19 +282,24 @@ void op_apply(stmg_ctx* c, DevLevel<T>& D, const T* x, const T* b, T* y, int mod
 }
 
 template <typename T>
-void op_vanka(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x) {
+void op_vanka(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x, bool xzero = false) {
+  // xzero: x holds no values yet and starts at 0
   T om = (T)c->p.omega;
-  if (c->p.vanka_mode == STMG_VANKA_DENSE)
+  if (c->p.vanka_mode == STMG_VANKA_DENSE) {
+    if (xzero) HIPCHK(launch_fill<T>(x, T(0), D.ndofs, c->stream));
     HIPCHK(launch_vanka_dense<T>(D.a, D.dense, r, x, om, c->stream));
-  else
-    HIPCHK(launch_vanka_factored<T>(D.a, D.Asw, D.Bm, D.F, D.Hinv, D.coef, r, x, om, D.E, c->stream));
+  } else {
+    HIPCHK(launch_vanka_factored<T>(D.a, D.Asw, D.Bm, D.F, D.Hinv, D.coef, r, x, om, D.E, c->stream, true, xzero));
+  }
 }
 
 template <typename T>
 void learned_step(stmg_ctx* c, DevLevel<T>& D, int level, const T* b, T* x);
 
+// zero_start: x starts at 0 (its contents are ignored; with steps == 0 it is set to 0)
 template <typename T>
 void op_smooth(stmg_ctx* c, DevLevel<T>& D, const T* b, T* x, int steps, bool zero_start, int level = -1) {
+  if (zero_start && steps == 0) HIPCHK(launch_fill<T>(x, T(0), D.ndofs, c->stream));
   for (int s = 0; s < steps; ++s) {
     const T* r = b;
     if (!(zero_start && s == 0)) {
@@ -302,7 +307,7 @@ void op_smooth(stmg_ctx* c, DevLevel<T>& D, const T* b, T* x, int steps, bool ze
       r = D.r;
     }
     if (c->phase_timing) c->t_smooth.a(c->stream);
-    op_vanka<T>(c, D, r, x);
+    op_vanka<T>(c, D, r, x, zero_start && s == 0);
     if (c->phase_timing) c->t_smooth.b(c->stream);
     if (level >= 0) learned_step<T>(c, D, level, b, x);
   }
@@ -454,8 +459,7 @@ void vcycle(stmg_ctx* c, Hier<T>& H, int l) {
     HIPCHK(launch_coarse<T>(D.a.slab, D.a.Mv, D.a.nt, D.a.N, c->Cinv, c->Cg, D.b, D.x, c->stream));
     return;
   }
-  HIPCHK(launch_fill<T>(D.x, T(0), D.ndofs, c->stream));
-  op_smooth<T>(c, D, D.b, D.x, c->p.nu_pre, true, l);                    // presmoothing
+  op_smooth<T>(c, D, D.b, D.x, c->p.nu_pre, true, l);                    // presmoothing from x = 0
   op_apply<T>(c, D, D.x, D.b, D.r, 1);                                   // residual
   op_restrict<T>(c, H, l, D.r, H.L[l + 1].b);                            // restriction
   vcycle<T>(c, H, l + 1);                                                // coarse-grid correction
