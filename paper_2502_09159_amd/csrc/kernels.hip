@@ -607,8 +607,10 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
   typedef typename mfma_vec<T>::v4 v4;
   const int N = L.N, lgN = N == 1 ? 0 : (N == 2 ? 1 : (N == 4 ? 2 : 3)), DN = D * N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* RZ = reinterpret_cast<T*>(smem_raw);  // R (B-operand order), then Z (row-major MP x DNP)
-  T* sB = RZ + MP * DNP;                   // B of this cell, [l][comp][i]
+  // Z rows are padded by one value (ZS): consecutive rows fall on consecutive banks
+  constexpr int ZS = DNP + 1;
+  T* RZ = reinterpret_cast<T*>(smem_raw);  // R (B-operand order), then Z (row-major MP x ZS)
+  T* sB = RZ + MP * ZS;                    // B of this cell, [comp][i][l] (l fastest: no bank conflicts)
   T* Rp = sB + C * D * NL;                 // pressure residual [q][n]
   T* S = Rp + P * 8;
   T* YP = S + P * 8;
@@ -631,7 +633,8 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
 
   // ---- R in B-operand order, B and the pressure residual.  R is read one
   // x-row of a cell (Q consecutive nodes, one vector load) per item: items
-  // (row, a, comp, n); Dirichlet entries are zeroed in registers.  Padding
+  // (n, comp, row, a), n fastest (so that the 16-byte LDS stores of a wave
+  // spread over all banks); Dirichlet entries are zeroed in registers.  Padding
   // entries of R (K >= M or column >= d N) are zeroed separately.  Loads
   // complete in issue order, so the loads this phase waits for are issued
   // first, then the A_s^{-1} fragments of the first row tile (consumed only
@@ -649,9 +652,8 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
 #pragma unroll
     for (int e = 0; e < IMAX; ++e) {
       const int it = min(tid + 256 * e, nitems - 1);
-      const int row = it % ROWS, rest = it / ROWS;  // rest = (a, col)
-      const int a = rest % NT, col = rest / NT;
-      const int comp = col >> lgN, n = col & (N - 1);
+      const int n = it & (N - 1), rest = (it >> lgN) / D, comp = (it >> lgN) - rest * D;
+      const int row = rest % ROWS, a = rest / ROWS;
       const int iy = row % Q, iz = row / Q;
       const int gy = cc[1] * (Q - 1) + iy, gz = D == 3 ? cc[2] * (Q - 1) + iz : 1;
       rok[e] = tid + 256 * e < nitems && gy > 0 && gy < L.nn - 1 && gz > 0 && (D == 2 || gz < L.nn - 1);
@@ -680,8 +682,8 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
     for (int e = 0; e < IMAX; ++e) {
       const int it = tid + 256 * e;
       if (it < nitems) {
-        const int row = it % ROWS, rest = it / ROWS;
-        const int a = rest % NT, col = rest / NT;
+        const int n = it & (N - 1), rest = (it >> lgN) / D, comp = (it >> lgN) - rest * D;
+        const int row = rest % ROWS, a = rest / ROWS, col = comp * N + n;
         const int K0 = a * NL + row * Q;
         const int ct = col / 16, jj = col % 16;
         // Dirichlet rows, and Dirichlet nodes at the ends of the row (x = 0, x = 1)
@@ -696,8 +698,13 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
       }
     }
 #pragma unroll
-    for (int e = 0; e < PB; ++e)
-      if (tid + 256 * e < C * D * NL) sB[tid + 256 * e] = bv[e];
+    for (int e = 0; e < PB; ++e) {
+      const int idx = tid + 256 * e;  // global order [l][comp][i]
+      if (idx < C * D * NL) {
+        const int l = idx / (D * NL), ci = idx - l * (D * NL);
+        sB[ci * C + l] = bv[e];
+      }
+    }
 #pragma unroll
     for (int e = 0; e < PR; ++e)
       if (tid + 256 * e < P * N) Rp[tid + 256 * e] = pv[e];
@@ -735,28 +742,37 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
       for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          RZ[(t * 16 + mfma_vec<T>::row(lane, v)) * DNP + ct * 16 + lane % 16] = acc[it][ct][v];
+          RZ[(t * 16 + mfma_vec<T>::row(lane, v)) * ZS + ct * 16 + lane % 16] = acc[it][ct][v];
   }
-  // F rows and H^{-1} columns of this thread, issued now (the A fragments are
-  // dead) so that their latency overlaps the Schur complement
+  // F and H^{-1} rows of this thread (16-byte loads), issued now (the A
+  // fragments are dead) so that their latency overlaps the Schur complement
   constexpr int RPT = (D * M + 255) / 256;  // velocity rows per thread
   constexpr int HPT = (P * 8 + 255) / 256;  // (pp, n) items per thread, N <= 8
-  const T* Fc = F + cell * (int64_t)D * M * P;
-  const T* H = Hinv + cell * (int64_t)P * P;
+  constexpr int P4 = (P + 3) / 4 * 4;  // row length of F and H^{-1} (vanka_row_pad)
+  const T* Fc = F + cell * (int64_t)D * M * P4;
+  const T* H = Hinv + cell * (int64_t)P * P4;
   T fv[RPT][P], hv[HPT][P], xp[HPT];
   // (unconditional loads from clamped addresses: exact wait counts)
 #pragma unroll
   for (int j = 0; j < HPT; ++j) {
     const int t = min(tid + 256 * j, P * N - 1), pp = t >> lgN, n = t & (N - 1);
+    {
+      T hrow[P4];
+      __builtin_memcpy(hrow, __builtin_assume_aligned(H + pp * P4, 16), sizeof(T) * P4);
 #pragma unroll
-    for (int q = 0; q < P; ++q) hv[j][q] = H[q * P + pp];
+      for (int q = 0; q < P; ++q) hv[j][q] = hrow[q];
+    }
     xp[j] = x[pidx(L, n, pp / C, cell, pp % C)];
   }
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
     const int row2 = min(tid + 256 * j, D * M - 1);
+    {
+      T frow[P4];
+      __builtin_memcpy(frow, __builtin_assume_aligned(Fc + (int64_t)row2 * P4, 16), sizeof(T) * P4);
 #pragma unroll
-    for (int q = 0; q < P; ++q) fv[j][q] = Fc[((row2 / M) * P + q) * M + row2 % M];
+      for (int q = 0; q < P; ++q) fv[j][q] = frow[q];
+    }
   }
   __syncthreads();
   const T* Z = RZ;
@@ -768,7 +784,7 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
 #pragma unroll
     for (int comp = 0; comp < D; ++comp)
 #pragma unroll 16
-      for (int i = 0; i < NL; ++i) s += sB[(l * D + comp) * NL + i] * Z[(a * NL + i) * DNP + comp * N + n];
+      for (int i = 0; i < NL; ++i) s += sB[(comp * NL + i) * C + l] * Z[(a * NL + i) * ZS + comp * N + n];
     S[q * N + n] = -sc[a] * s - Rp[q * N + n];
   }
   __syncthreads();
@@ -800,7 +816,7 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
       if (n >= N) break;
-      T v = Z[row * DNP + comp * N + n];
+      T v = Z[row * ZS + comp * N + n];
 #pragma unroll
       for (int q = 0; q < P; ++q) v -= f[q] * YP[q * N + n];
       E[((int64_t)(n * NT + a) * D + comp) * NE + eo] = v;
@@ -824,7 +840,7 @@ static hipError_t vanka_fact_impl(const LevelArgs& L, const T* Asw, const T* Bm,
   if (MP / 16 > 16) return hipErrorInvalidValue;  // at most 4 row tiles per wave
   const int64_t ncells = L.Mp / L.C;
   const int DN = D * L.N;
-  auto shm = [&](int dnp) { return sizeof(T) * ((size_t)MP * dnp + (size_t)C * D * NL + 3 * (size_t)P * 8 + 8); };
+  auto shm = [&](int dnp) { return sizeof(T) * ((size_t)MP * (dnp + 1) + (size_t)C * D * NL + 3 * (size_t)P * 8 + 8); };
   auto run = [&](auto kern, size_t bytes) -> hipError_t {
     if (bytes > 65536) {  // beyond the default dynamic LDS limit
       hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

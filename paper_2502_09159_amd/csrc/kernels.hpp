@@ -51,6 +51,9 @@ template <typename T>
 hipError_t launch_vanka_factored(const LevelArgs& L, const T* Asw, const T* Bm, const T* F, const T* Hinv,
                                  const T* coef, const T* r, T* x, T omega, T* E, hipStream_t s,
                                  bool gather = true, bool xzero = false);
+// Row length of the device copies of F (per component: m rows of P) and of
+// H^{-1} (P rows of P): P padded to a multiple of 4 values.
+inline int vanka_row_pad(int P) { return (P + 3) / 4 * 4; }
 // Position of A_s^{-1}[row][k] inside one cell's swizzled block (mp x mp):
 // row tile t = row/16, k chunk kb = k/16, lane = row%16 + 16*((k%16)/4), slot k%4.
 inline int64_t vanka_swizzle_index(int mp, int row, int k) {

@@ -221,8 +221,22 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
                   (T)V.As_inv[((size_t)cl * m + k) * m + row];
         D.Asw = c->pool.upload<T>(sw, s);
         D.Bm = c->pool.upload<T>(V.Bm, s);
-        D.F = c->pool.upload<T>(V.F, s);
-        D.Hinv = c->pool.upload<T>(V.Hinv, s);
+        // F and H^{-1} row by row (each row padded to a multiple of 4 values),
+        // so that a thread reads a row with 16-byte loads
+        const int P = V.P, P4 = vanka_row_pad(P);
+        std::vector<T> Fr((size_t)L.ncells * L.d * m * P4, T(0)), Hr((size_t)L.ncells * P * P4, T(0));
+        for (int64_t cl = 0; cl < L.ncells; ++cl) {
+          for (int comp = 0; comp < L.d; ++comp)
+            for (int q = 0; q < P; ++q)
+              for (int row = 0; row < m; ++row)
+                Fr[(((size_t)cl * L.d + comp) * m + row) * P4 + q] =
+                    (T)V.F[(((size_t)cl * L.d + comp) * P + q) * m + row];
+          for (int q = 0; q < P; ++q)
+            for (int pp = 0; pp < P; ++pp)
+              Hr[((size_t)cl * P + pp) * P4 + q] = (T)V.Hinv[((size_t)cl * P + q) * P + pp];
+        }
+        D.F = c->pool.upload<T>(Fr, s);
+        D.Hinv = c->pool.upload<T>(Hr, s);
       }
     }
   }
