@@ -308,23 +308,26 @@ void op_vanka(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x, bool xzero = false)
 }
 
 template <typename T>
-void learned_step(stmg_ctx* c, DevLevel<T>& D, int level, const T* b, T* x);
+bool learned_step(stmg_ctx* c, DevLevel<T>& D, int level, const T* b, T* x);
 
-// zero_start: x starts at 0 (its contents are ignored; with steps == 0 it is set to 0)
+// zero_start: x starts at 0 (its contents are ignored; with steps == 0 it is set to 0).
+// Returns whether D.r holds b - S x on exit (left there by a learned step).
 template <typename T>
-void op_smooth(stmg_ctx* c, DevLevel<T>& D, const T* b, T* x, int steps, bool zero_start, int level = -1) {
+bool op_smooth(stmg_ctx* c, DevLevel<T>& D, const T* b, T* x, int steps, bool zero_start, int level = -1) {
   if (zero_start && steps == 0) HIPCHK(launch_fill<T>(x, T(0), D.ndofs, c->stream));
+  bool r_current = false;
   for (int s = 0; s < steps; ++s) {
     const T* r = b;
     if (!(zero_start && s == 0)) {
-      op_apply<T>(c, D, x, b, D.r, 1);
+      if (!r_current) op_apply<T>(c, D, x, b, D.r, 1);
       r = D.r;
     }
     if (c->phase_timing) c->t_smooth.a(c->stream);
     op_vanka<T>(c, D, r, x, zero_start && s == 0);
     if (c->phase_timing) c->t_smooth.b(c->stream);
-    if (level >= 0) learned_step<T>(c, D, level, b, x);
+    r_current = level >= 0 && learned_step<T>(c, D, level, b, x);
   }
+  return r_current;
 }
 
 template <typename T>
@@ -446,11 +449,13 @@ void learned_correction_at(stmg_ctx* c, int level, int route, const T* r, T* cv)
   op_prolongate_add<T>(c, H, level, cc, cv);
 }
 
+// Returns whether it ran: then D.r holds b - S x for the x it leaves (the
+// residual after the update is r - alpha w, so the caller need not apply S again).
 template <typename T>
-void learned_step(stmg_ctx* c, DevLevel<T>& D, int level, const T* b, T* x) {
-  if (!c->learned_on || c->learned_disabled || !c->net_ready) return;
+bool learned_step(stmg_ctx* c, DevLevel<T>& D, int level, const T* b, T* x) {
+  if (!c->learned_on || c->learned_disabled || !c->net_ready) return false;
   const int route = net_route(c, level);
-  if (route == 0 || (route == 2 && c->learned_reading != 1)) return;
+  if (route == 0 || (route == 2 && c->learned_reading != 1)) return false;
   T* cv = static_cast<T*>(c->lsave[2 * level]);
   T* wv = static_cast<T*>(c->lsave[2 * level + 1]);
   op_apply<T>(c, D, x, b, D.r, 1);
@@ -459,9 +464,12 @@ void learned_step(stmg_ctx* c, DevLevel<T>& D, int level, const T* b, T* x) {
   const double rw = dot_t<T>(c, D.r, wv, D.ndofs), ww = dot_t<T>(c, wv, wv, D.ndofs);
   if (!(rw > 0.0) || !(ww > 0.0) || !std::isfinite(rw / ww)) {
     c->learned_disabled = true;
-    return;
+    return true;  // x unchanged: D.r = b - S x
   }
-  HIPCHK(launch_axpy<T>(x, (T)(rw / ww), cv, D.ndofs, c->stream));
+  const T alpha = (T)(rw / ww);
+  HIPCHK(launch_axpy<T>(x, alpha, cv, D.ndofs, c->stream));
+  HIPCHK(launch_axpy<T>(D.r, -alpha, wv, D.ndofs, c->stream));
+  return true;
 }
 
 // x_l = V(b_l) on level l (zero initial guess), Alg. 1.
@@ -473,8 +481,8 @@ void vcycle(stmg_ctx* c, Hier<T>& H, int l) {
     HIPCHK(launch_coarse<T>(D.a.slab, D.a.Mv, D.a.nt, D.a.N, c->Cinv, c->Cg, D.b, D.x, c->stream));
     return;
   }
-  op_smooth<T>(c, D, D.b, D.x, c->p.nu_pre, true, l);                    // presmoothing from x = 0
-  op_apply<T>(c, D, D.x, D.b, D.r, 1);                                   // residual
+  if (!op_smooth<T>(c, D, D.b, D.x, c->p.nu_pre, true, l))               // presmoothing from x = 0
+    op_apply<T>(c, D, D.x, D.b, D.r, 1);                                 // residual (unless left there)
   op_restrict<T>(c, H, l, D.r, H.L[l + 1].b);                            // restriction
   vcycle<T>(c, H, l + 1);                                                // coarse-grid correction
   op_prolongate_add<T>(c, H, l, H.L[l + 1].x, D.x);                      // prolongation and correction
