@@ -449,8 +449,11 @@ __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __res
     }
     return;
   }
+  // KIND 0 reads the operator's grid layout, KIND 1 the smoother's cell-major one
+  constexpr bool CM = KIND == 1;
+  constexpr int NLQ = D == 3 ? QQ * QQ * QQ : QQ * QQ;
   const int W = QQ * L.n;
-  const int64_t NE = D == 3 ? (int64_t)W * W * W : (int64_t)W * W;
+  const int64_t NE = CM ? (int64_t)(L.Mp / L.C) * NLQ : (D == 3 ? (int64_t)W * W * W : (int64_t)W * W);
   const T* Ef = E + field * NE;
   const int ny = (gy % q == 0) ? 2 : 1, nz = D == 3 ? ((gz % q == 0) ? 2 : 1) : 1;
   const int dy = gy + gy / q, dz = gz + gz / q;
@@ -464,7 +467,17 @@ __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __res
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
       if (v >= ny) break;
-      const T* er = Ef + (D == 3 ? (int64_t)(dz - u) * W * W : 0) + (int64_t)(dy - v) * W + (int64_t)QQ * c;
+      // the x-row (duplicated y index dy - v, z index dz - u) of cell c; er[-1]
+      // is the last node of the row in cell c - 1
+      const T* er;
+      if constexpr (CM) {
+        const int DY = dy - v, DZ = D == 3 ? dz - u : 0;
+        const int64_t cellc = c + (int64_t)L.n * ((DY / QQ) + (D == 3 ? (int64_t)L.n * (DZ / QQ) : 0));
+        er = Ef + cellc * NLQ + ((D == 3 ? (DZ % QQ) * QQ : 0) + DY % QQ) * QQ;
+      } else {
+        er = Ef + (D == 3 ? (int64_t)(dz - u) * W * W : 0) + (int64_t)(dy - v) * W + (int64_t)QQ * c;
+      }
+      const T* el = CM ? er - NLQ + QQ : er;  // el[-1]: last node of the row in cell c - 1
       T ev[q];
       if constexpr (QQ == 4 && sizeof(T) == 4) {  // 16-byte aligned
         const float4 t4 = *reinterpret_cast<const float4*>(er);
@@ -478,7 +491,7 @@ __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __res
       }
 #pragma unroll
       for (int j = 0; j < q; ++j) own[j] += ev[j];
-      if (c > 0) below += er[-1];
+      if (c > 0) below += el[-1];
     }
   }
   const T vyz = T(ny * nz);
@@ -802,24 +815,21 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
   }
   __syncthreads();
 
-  // ---- velocity: y = z - F y_p into the cell-local scratch E
-  const int W = Q * L.n;
-  const int64_t NE = D == 3 ? (int64_t)W * W * W : (int64_t)W * W;
+  // ---- velocity: y = z - F y_p into the cell-local scratch E (cell-major:
+  // the work group writes whole cache lines)
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
     const int row2 = tid + 256 * j;
     if (row2 >= D * M) break;
     const int comp = row2 / M, row = row2 % M, a = row / NL, i = row % NL;
     const T(&f)[P] = fv[j];
-    const int64_t eo = (cc[0] * Q + i % Q) + (int64_t)W * ((cc[1] * Q + (i / Q) % Q) +
-                                                           (D == 3 ? (int64_t)W * (cc[2] * Q + i / (Q * Q)) : 0));
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
       if (n >= N) break;
       T v = Z[row * ZS + comp * N + n];
 #pragma unroll
       for (int q = 0; q < P; ++q) v -= f[q] * YP[q * N + n];
-      E[((int64_t)(n * NT + a) * D + comp) * NE + eo] = v;
+      E[e_index(L, (int64_t)(n * NT + a) * D + comp, cell, i)] = v;
     }
   }
 }

@@ -14,17 +14,18 @@ struct LevelArgs {
   int64_t nodes, Mv, Mp, slab;
 };
 
-// Cell-local scratch E of the operator and of the smoother: per field
-// f = (n nt + a) d + comp a grid of (Q n)^d duplicated nodes, x fastest, in
-// which local node (ix, iy, iz) of cell (cx, cy, cz) sits at
-// (cx Q + ix, cy Q + iy, cz Q + iz): every cell keeps its own copy of the
-// nodes it shares, and a row of global nodes reads contiguous memory.
+// Cell-local scratch E (every cell keeps its own copy of the nodes it
+// shares; a gather kernel sums the copies of each node), per field
+// f = (n nt + a) d + comp, in one of two layouts:
+//  * operator (grid): a grid of (Q n)^d duplicated nodes, x fastest, in which
+//    local node (ix, iy, iz) of cell (cx, cy, cz) sits at (cx Q + ix,
+//    cy Q + iy, cz Q + iz), so that a row of global nodes reads contiguous
+//    memory (the operator kernel writes whole cells per wave anyway);
+//  * smoother (cell-major): cell by cell, local node i = ix + Q (iy + Q iz)
+//    fastest, so that the one-cell-per-work-group smoother writes whole
+//    cache lines (e_index).
 __device__ __forceinline__ int64_t e_index(const LevelArgs& L, int64_t field, int64_t cell, int i) {
-  const int W = L.Q * L.n;
-  const int64_t NE = L.d == 3 ? (int64_t)W * W * W : (int64_t)W * W;
-  const int ix = i % L.Q, iy = (i / L.Q) % L.Q, iz = i / (L.Q * L.Q);
-  const int cx = (int)(cell % L.n), cy = (int)((cell / L.n) % L.n), cz = (int)(cell / ((int64_t)L.n * L.n));
-  return field * NE + (cx * L.Q + ix) + (int64_t)W * ((cy * L.Q + iy) + (int64_t)W * (cz * L.Q + iz));
+  return (field * (L.Mp / L.C) + cell) * L.nloc + i;
 }
 
 // Small per-level tables, in the arithmetic type T, packed as
