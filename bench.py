@@ -89,6 +89,17 @@ def apply_cell_flops(w):
     return 2.0 * ncells * N * (interp + d * nt * per_field + pres)
 
 
+def apply_cell_bytes(w):
+    """Algorithmic HBM bytes of the operator's cell kernel on the finest level
+    (FP32): the input vector once, the per-Gauss-point metric once (JxW, JxW
+    J^-1 and nu JxW J^-1 J^-T: 1 + d^2 + d(d+1)/2 values a point), the
+    cell-local velocity results E written once and the pressure rows written
+    once."""
+    d, nl, nt, C, N, ncells, ndofs = element_sizes(w)
+    metric = 1 + d * d + d * (d + 1) // 2
+    return 4.0 * (ndofs + ncells * metric * nl + ncells * d * nt * nl * N + ncells * C * nt * N)
+
+
 def measured_traffic(kernel_prefix, grid):
     """Scaled HBM bytes per launch of a kernel from the counter summary kept
     in profiles/ (FETCH_SIZE and WRITE_SIZE runs), or None when the kernel
@@ -231,6 +242,10 @@ def main():
                       "unit": "TFLOP/s", "frac": round(flops / (cell_ev_ms * 1e-3) / 1e12 / alu_peak, 4),
                       "kernel": "k_apply (finest level, cell kernel)", "ms_per_launch": round(cell_ev_ms, 4),
                       "ms_library_events": round(cell_ms, 4), "flops": flops}
+    abytes = apply_cell_bytes(w)
+    roofline_apply["hbm_view"] = {"achieved": round(abytes / (cell_ev_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                  "unit": "GB/s", "frac": round(abytes / (cell_ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "algorithmic_bytes": abytes}
     op_ms = S.kernel_time(1, level=0, reps=reps)
 
     extra = {}

@@ -48,7 +48,7 @@ typedef enum {
   STMG_EDEVICE = -3,      /* a HIP runtime call failed */
   STMG_ENOCONV = -4,      /* solve reached max_it before the tolerance */
   STMG_ESINGULAR = -5,    /* a local or coarse factorisation broke down */
-  STMG_EUNSUPPORTED = -6  /* feature not available in this build */
+  STMG_EUNSUPPORTED = -6  /* configuration the library does not support */
 } stmg_status;
 
 typedef struct stmg_ctx stmg_ctx;

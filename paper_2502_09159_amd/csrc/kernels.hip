@@ -2,8 +2,11 @@
 //
 // Data layout (Eq. (DefX)): X = (V_1, P_1, ..., V_N, P_N), V_n^a component-major
 // over the global Gauss-Lobatto nodes, P_n^a cell-major over Legendre modes.
-// Scatter-adds to velocity nodes shared by cells are made race-free and
-// deterministic by 2^d-colouring the cells (cells of one colour share no node).
+// Velocity contributions of the cells to the nodes they share go to a
+// cell-local scratch E (one copy per cell) and are summed per node by gather
+// kernels in a fixed order: no atomics, bit-reproducible results.  Only the
+// dense-inverse smoother (a test path) adds into the nodes directly, race-free
+// by 2^d-colouring the cells (cells of one colour share no node).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -83,7 +86,7 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid64, int64_t nblocks64) {
 // subinterval (the jump term) in registers.  Geometry per Gauss point is
 // precomputed: JxW, JxW J^{-1} and nu JxW J^{-1} J^{-T}.
 // Velocity contributions go to the cell-local scratch E (summed per node by
-// k_apply_gather in a fixed order); pressure rows are written directly.
+// k_node_gather in a fixed order); pressure rows are written directly.
 // =====================================================================
 namespace {
 
@@ -552,8 +555,7 @@ static hipError_t apply_impl(const LevelArgs& L, const T* geo, const T* tab, con
   int64_t nchunk = std::min<int64_t>(L.N, std::max<int64_t>(1, (4096 + 4 * nbx - 1) / (4 * nbx)));
   const int nper = (int)((L.N + nchunk - 1) / nchunk);
   nchunk = (L.N + nper - 1) / nper;
-  k_apply<T, D, Q, NT><<<dim3((unsigned)nbx, (unsigned)nchunk), 256, 0, s>>>(L, geo, tab, x, b, y,
-                                                                                             E, mode, nper);
+  k_apply<T, D, Q, NT><<<dim3((unsigned)nbx, (unsigned)nchunk), 256, 0, s>>>(L, geo, tab, x, b, y, E, mode, nper);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !gather) return e;
   return node_gather<T, 0>(L, E, x, b, y, mode, T(0), s);
@@ -580,7 +582,7 @@ hipError_t launch_apply(const LevelArgs& L, const T* geo, const T* tab, const T*
 //   Z = A_s^{-1} R               (MFMA: mp x mp times mp x (d N), one pass over A_s^{-1})
 //   y_p = H^{-1} (D Z - r_p),    y_c = z_c - F_c y_p
 //   x_p += omega y_p             (pressure dofs belong to one cell)
-//   E   = y_v                    (velocity: summed per node by k_vanka_gather)
+//   E   = y_v                    (velocity: summed per node by k_node_gather, KIND 1)
 // MFMA 16x16x4 operand order: lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // accumulator element v holds D[row][l%16] with row = 4 (l/16) + v for FP32
 // and row = l/16 + 4 v for FP64 (both checked on gfx950).
@@ -1710,13 +1712,14 @@ __global__ __launch_bounds__(256) void k_lcgs_a(double* __restrict__ V, int64_t 
   block_sums_out<NVM>(acc, j + 1, sh, partial);
 }
 
-// Second pass: w -= sum_{k<nv} h_k V_k, then partial sums of V_k . w (updated
-// w) for k < nv and of w . w (index nv).  The basis values stay in registers
+// Second pass: w -= sum_{k<nv} h_k V_k (also rounded to FP32 into w32 when
+// given), then partial sums of V_k . w (updated w) for k < nv and of w . w
+// (index nv).  The basis values stay in registers
 // up to 16 vectors; beyond, the second use reads them again (L2).
 template <int NVM>
 __global__ __launch_bounds__(256) void k_axpy_mdot(double* __restrict__ w, const double* __restrict__ V,
                                                    int64_t ldv, int nv, const double* __restrict__ h, int64_t n,
-                                                   double* __restrict__ partial) {
+                                                   double* __restrict__ partial, float* __restrict__ w32) {
   constexpr bool KEEP = NVM <= kCgsChunk;
   constexpr int CN = NVM < kCgsChunk ? NVM : kCgsChunk;
   __shared__ double sh[(NVM + 1) * 4];
@@ -1736,6 +1739,7 @@ __global__ __launch_bounds__(256) void k_axpy_mdot(double* __restrict__ w, const
     }
     const double wi = w0 - s;
     w[i] = wi;
+    if (w32) w32[i] = (float)wi;  // the next direction in FP32 (the mixed V-cycle's input)
 #pragma unroll
     for (int c = 0; c < NVM; c += kCgsChunk) {
       if constexpr (!KEEP) {
@@ -1779,22 +1783,22 @@ __global__ __launch_bounds__(256) void k_fused_final(const double* __restrict__ 
 template <int NVM>
 static void lcgs2_impl(double* V, int64_t ldv, int j, int pending, const double* u, const double* h2_prev,
                        double invb, double* w, int64_t n, double* partial, double* h1, double* h2n,
-                       hipStream_t s) {
+                       float* w32, hipStream_t s) {
   const int nv = j + 1;
   k_lcgs_a<NVM><<<kFusedBlocks, 256, 0, s>>>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial);
   k_fused_final<<<nv, 256, 0, s>>>(partial, nv, h1);
-  k_axpy_mdot<NVM><<<kFusedBlocks, 256, 0, s>>>(w, V, ldv, nv, h1, n, partial);
+  k_axpy_mdot<NVM><<<kFusedBlocks, 256, 0, s>>>(w, V, ldv, nv, h1, n, partial, w32);
   k_fused_final<<<nv + 1, 256, 0, s>>>(partial, nv + 1, h2n);
 }
 
 hipError_t launch_lcgs2(double* V, int64_t ldv, int j, int pending, const double* u, const double* h2_prev,
-                        double invb, double* w, int64_t n, double* partial, double* h1, double* h2n,
+                        double invb, double* w, int64_t n, double* partial, double* h1, double* h2n, float* w32,
                         hipStream_t s) {
   const int nv = j + 1;
   if (j < 0 || nv > kMaxFused || (!pending && j != 0)) return hipErrorInvalidValue;
 #define STMG_LC(K) \
   if (nv <= K) {   \
-    lcgs2_impl<K>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial, h1, h2n, s); \
+    lcgs2_impl<K>(V, ldv, j, pending, u, h2_prev, invb, w, n, partial, h1, h2n, w32, s); \
     return hipGetLastError();                                                     \
   }
   STMG_LC(4) STMG_LC(8) STMG_LC(12) STMG_LC(16) STMG_LC(20) STMG_LC(24) STMG_LC(28) STMG_LC(32)
@@ -1821,12 +1825,28 @@ hipError_t launch_combine(double* x, const double* Z, int64_t ldz, int nv, const
   k_multi_axpy<<<nblk(n), 256, 0, s>>>(x, Z, ldz, nv, y, n, 1.0);
   return hipGetLastError();
 }
-__global__ void k_scale_copy(double* y, const double* x, double inv, int64_t n) {
+__global__ void k_combine_f32(double* __restrict__ x, const float* __restrict__ Z, int64_t ldz, int nv,
+                              const double* __restrict__ y, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = x[i] * inv;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = 0; k < nv; ++k) s += y[k] * (double)Z[(int64_t)k * ldz + i];
+  x[i] += s;
 }
-hipError_t launch_scale_copy(double* y, const double* x, double inv, int64_t n, hipStream_t s) {
-  k_scale_copy<<<nblk(n), 256, 0, s>>>(y, x, inv, n);
+hipError_t launch_combine_f32(double* x, const float* Z, int64_t ldz, int nv, const double* y, int64_t n,
+                              hipStream_t s) {
+  k_combine_f32<<<nblk(n), 256, 0, s>>>(x, Z, ldz, nv, y, n);
+  return hipGetLastError();
+}
+__global__ void k_scale_copy(double* y, const double* x, double inv, int64_t n, float* y32) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = x[i] * inv;
+  y[i] = v;
+  if (y32) y32[i] = (float)v;
+}
+hipError_t launch_scale_copy(double* y, const double* x, double inv, int64_t n, hipStream_t s, float* y32) {
+  k_scale_copy<<<nblk(n), 256, 0, s>>>(y, x, inv, n, y32);
   return hipGetLastError();
 }
 

@@ -131,17 +131,21 @@ hipError_t launch_dot(const T* a, const T* b, int64_t n, double* partial, double
 // partial needs (nv + 1) * 2048 doubles; nv <= kMaxFused.  Sums in a fixed
 // order.
 constexpr int kMaxFused = 64;
+// w32 (may be null): receives w after pass 2 rounded to FP32.
 hipError_t launch_lcgs2(double* V, int64_t ldv, int j, int pending, const double* u, const double* h2_prev,
-                        double invb, double* w, int64_t n, double* partial, double* h1, double* h2n,
+                        double invb, double* w, int64_t n, double* partial, double* h1, double* h2n, float* w32,
                         hipStream_t s);
 // w -= sum_i h_i V_i (h on device)
 hipError_t launch_multi_axpy(double* w, const double* V, int64_t ldv, int nv, const double* h, int64_t n,
                              hipStream_t s);
-// x += sum_i y_i Z_i
+// x += sum_i y_i Z_i (FP64 basis, or FP32 basis)
 hipError_t launch_combine(double* x, const double* Z, int64_t ldz, int nv, const double* y, int64_t n,
                           hipStream_t s);
-// scale: y = x / a
-hipError_t launch_scale_copy(double* y, const double* x, double inv, int64_t n, hipStream_t s);
+hipError_t launch_combine_f32(double* x, const float* Z, int64_t ldz, int nv, const double* y, int64_t n,
+                              hipStream_t s);
+// scale: y = x * inv (and y32 = y rounded to FP32, when y32 is given)
+hipError_t launch_scale_copy(double* y, const double* x, double inv, int64_t n, hipStream_t s,
+                             float* y32 = nullptr);
 // pressure mean removal per slice; mom: ncells x C moments; partial >= N nt 1024
 hipError_t launch_project_pressure(const LevelArgs& L, const double* mom, double volume, double* x,
                                    double* partial, hipStream_t s);

@@ -149,6 +149,8 @@ struct stmg_ctx {
   // FGMRES work
   double *V = nullptr, *Z = nullptr, *w = nullptr, *u = nullptr, *partial = nullptr, *dh = nullptr,
          *dtmp = nullptr;
+  float* Z32 = nullptr;    // mixed precision: the preconditioned basis, as the FP32 V-cycle leaves it
+  double* zt = nullptr;    // mixed precision: FP64 copy of the current basis vector
   int cap = 0;
   std::vector<double> history;
   bool phase_timing = false;
@@ -489,6 +491,21 @@ void vcycle(stmg_ctx* c, Hier<T>& H, int l) {
   op_smooth<T>(c, D, D.b, D.x, c->p.nu_post, false, l);                  // postsmoothing
 }
 
+// Mixed precision: z = V(b) with the finest FP32 level's b already holding
+// the input; the V-cycle writes its result straight into z (FP32).
+void precondition_f32(stmg_ctx* c, float* z) {
+  DevLevel<float>& D = c->H32.L[0];
+  struct Restore {
+    float*& x;
+    float* keep;
+    ~Restore() { x = keep; }
+  } restore{D.x, D.x};
+  if (c->phase_timing) c->t_vcyc.a(c->stream);
+  D.x = z;
+  vcycle<float>(c, c->H32, 0);
+  if (c->phase_timing) c->t_vcyc.b(c->stream);
+}
+
 // z = V(v) for FP64 vectors v, z (device), in the context's precision
 void precondition(stmg_ctx* c, const double* v, double* z) {
   if (c->phase_timing) c->t_vcyc.a(c->stream);
@@ -657,6 +674,7 @@ stmg_status stmg_setup(const stmg_params* p, stmg_ctx** out) {
     c->w = c->pool.alloc<double>(c->host[0].ndofs);
     c->u = c->pool.alloc<double>(c->host[0].ndofs);
     c->dtmp = c->pool.alloc<double>(c->host[0].ndofs);
+    if (c->mixed) c->zt = c->pool.alloc<double>(c->host[0].ndofs);
     // release host element matrices (kept: level sizes and tables)
     for (auto& L : c->host) {
       std::vector<double>().swap(L.Me);
@@ -681,6 +699,9 @@ stmg_status stmg_destroy(stmg_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   c->pool.release();
+  if (c->V) (void)hipFree(c->V);
+  if (c->Z) (void)hipFree(c->Z);
+  if (c->Z32) (void)hipFree(c->Z32);
   delete c;
   return STMG_OK;
 }
@@ -859,11 +880,15 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
       int64_t fit = (int64_t)(0.45 * (double)fr / (2.0 * ldv * sizeof(double)));
       int cap = (int)std::max<int64_t>(8, std::min<int64_t>(want, fit));
       if (cap > c->cap) {
-        if (c->V) { (void)hipFree(c->V); (void)hipFree(c->Z); }
+        if (c->V) (void)hipFree(c->V);
+        if (c->Z) (void)hipFree(c->Z);
+        if (c->Z32) (void)hipFree(c->Z32);
         c->V = nullptr;
         c->Z = nullptr;
+        c->Z32 = nullptr;
         HIPCHK(hipMalloc(&c->V, (size_t)cap * ldv * sizeof(double)));
-        HIPCHK(hipMalloc(&c->Z, (size_t)cap * ldv * sizeof(double)));
+        if (c->mixed) HIPCHK(hipMalloc(&c->Z32, (size_t)cap * ldv * sizeof(float)));
+        else HIPCHK(hipMalloc(&c->Z, (size_t)cap * ldv * sizeof(double)));
         c->cap = cap;
       }
     }
@@ -891,7 +916,8 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
       rel = bnorm > 0 ? beta / bnorm : 0.0;
       c->history.push_back(rel);
       if (bnorm == 0.0 || beta <= rtol * bnorm || total >= max_it) break;
-      HIPCHK(launch_scale_copy(c->V, c->w, 1.0 / beta, n, s));
+      // (mixed: the FP32 copy of V_0 is the first V-cycle's input)
+      HIPCHK(launch_scale_copy(c->V, c->w, 1.0 / beta, n, s, c->mixed ? c->H32.L[0].b : nullptr));
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       int j = 0;
@@ -904,15 +930,29 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
       double* uv = c->u;
       double invb = 0.0;
       while (j < m && total < max_it) {
-        double* zj = c->Z + (size_t)j * ldv;
-        precondition(c, j == 0 ? c->V : uv, zj);
-        if (c->phase_timing) c->t_op.a(s);
-        op_apply<double>(c, L0, zj, zj, wv, 0);
-        if (c->phase_timing) c->t_op.b(s);
+        if (c->mixed) {
+          // z_j = V(v_j) in FP32 straight into the basis (its FP32 input was
+          // written with v_j); w = S z_j in FP64 on its FP64 copy (an FP64
+          // operator reading FP32 input directly runs slower)
+          float* zj = c->Z32 + (size_t)j * ldv;
+          precondition_f32(c, zj);
+          HIPCHK(launch_cast_f2d(zj, c->zt, n, s));
+          if (c->phase_timing) c->t_op.a(s);
+          op_apply<double>(c, L0, c->zt, c->zt, wv, 0);
+          if (c->phase_timing) c->t_op.b(s);
+        } else {
+          double* zj = c->Z + (size_t)j * ldv;
+          precondition(c, j == 0 ? c->V : uv, zj);
+          if (c->phase_timing) c->t_op.a(s);
+          op_apply<double>(c, L0, zj, zj, wv, 0);
+          if (c->phase_timing) c->t_op.b(s);
+        }
         double* h1 = c->dh;
         double* h2n = c->dh + 256 + 128 * (j & 1);
         const double* h2p = c->dh + 256 + 128 * ((j + 1) & 1);
-        HIPCHK(launch_lcgs2(c->V, ldv, j, j > 0 ? 1 : 0, uv, h2p, invb, wv, n, c->partial, h1, h2n, s));
+        // (mixed: pass 2 also writes the next direction in FP32, the next V-cycle's input)
+        HIPCHK(launch_lcgs2(c->V, ldv, j, j > 0 ? 1 : 0, uv, h2p, invb, wv, n, c->partial, h1, h2n,
+                            c->mixed ? c->H32.L[0].b : nullptr, s));
         std::vector<double> hh(j + 1), h2(j + 2);
         HIPCHK(hipMemcpyAsync(hh.data(), h1, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(h2.data(), h2n, h2.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -953,7 +993,8 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
         y[i] = t / H[(size_t)i * m + i];
       }
       HIPCHK(hipMemcpyAsync(c->dh, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-      HIPCHK(launch_combine(x, c->Z, ldv, j, c->dh, n, s));
+      if (c->mixed) HIPCHK(launch_combine_f32(x, c->Z32, ldv, j, c->dh, n, s));
+      else HIPCHK(launch_combine(x, c->Z, ldv, j, c->dh, n, s));
     }
     HIPCHK(launch_project_pressure(L0.a, c->mom0, c->volume0, x, c->partial, s));
     HIPCHK(hipEventRecord(e1, s));
