@@ -1829,8 +1829,15 @@ __global__ void k_combine_f32(double* __restrict__ x, const float* __restrict__ 
                               const double* __restrict__ y, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  // 8 basis loads in flight at a time (indices past nv read the last vector, weight 0)
   double s = 0.0;
-  for (int k = 0; k < nv; ++k) s += y[k] * (double)Z[(int64_t)k * ldz + i];
+  for (int k0 = 0; k0 < nv; k0 += 8) {
+    float z[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) z[k] = Z[(int64_t)min(k0 + k, nv - 1) * ldz + i];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += (k0 + k < nv ? y[k0 + k] : 0.0) * (double)z[k];
+  }
   x[i] += s;
 }
 hipError_t launch_combine_f32(double* x, const float* Z, int64_t ldz, int nv, const double* y, int64_t n,

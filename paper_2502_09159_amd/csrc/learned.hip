@@ -39,10 +39,10 @@ constexpr int OFF_W1 = 0, OFF_W2 = 32 * 15 * 27, OFF_W3 = OFF_W2 + 32 * 32 * 27;
 // One convolution over the G samples in LDS: out[g][p][co] = sum_o sum_ci in[g][nbr(o,p)][ci] W.
 // frag: B operands, ((o KB + kb) CT + ct) 64 + lane, 4 BF16 each.
 // MODE 0: ReLU -> BF16 out (LDS);  1: FP32 out (LDS);  2: x relu'(act) -> BF16 out
-template <int CIP, int COP, int MODE>
+template <int CIP, int COP, int MODE, int GS = G>
 __device__ void conv_block(const uint16_t* __restrict__ in, const bf16x4* __restrict__ frag, void* out,
                            const uint16_t* __restrict__ act) {
-  constexpr int KB = CIP / 16, CT = COP / 16, RT = G * 2;
+  constexpr int KB = CIP / 16, CT = COP / 16, RT = GS * 2;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   f32x4 acc[RT / 4][CT];
 #pragma unroll
@@ -91,6 +91,30 @@ __device__ void conv_block(const uint16_t* __restrict__ in, const bf16x4* __rest
 
 // ------------------------------------------------------------ forward
 // x: [s][32][16] BF16 -> h1, h2 [s][32][32] BF16 (optional) -> y [s][32][16] FP32
+// Inference only (no activations kept): GI samples per work group, with two
+// LDS regions reused layer by layer (A: h1, then y; B: x, then h2), so that
+// twice the samples share each weight fragment a wave reads.
+constexpr int GI = 16;
+__global__ __launch_bounds__(256) void k_net_infer(const uint16_t* __restrict__ x, const bf16x4* __restrict__ fw,
+                                                   float* __restrict__ y, int64_t count) {
+  static_assert(GI * 32 * 16 * sizeof(float) == GI * 32 * 32 * sizeof(uint16_t), "region A holds h1, then y");
+  __shared__ __align__(16) uint16_t sA[GI * 32 * 32];
+  __shared__ __align__(16) uint16_t sB[GI * 32 * 32];
+  const int64_t s0 = (int64_t)blockIdx.x * GI;
+  const int ns = (int)min<int64_t>(GI, count - s0);
+  for (int t = threadIdx.x; t < GI * 32 * 16; t += blockDim.x) sB[t] = (t / 512) < ns ? x[s0 * 512 + t] : 0;
+  __syncthreads();
+  conv_block<16, 32, 0, GI>(sB, fw, sA, nullptr);
+  __syncthreads();
+  conv_block<32, 32, 0, GI>(sA, fw + F1 / 4, sB, nullptr);
+  __syncthreads();
+  float* sy = reinterpret_cast<float*>(sA);
+  conv_block<32, 16, 1, GI>(sB, fw + (F1 + F2) / 4, sy, nullptr);
+  __syncthreads();
+  for (int t = threadIdx.x; t < ns * 512; t += blockDim.x) y[s0 * 512 + t] = sy[t];
+}
+
+// Training forward: keeps the hidden activations for the backward pass.
 __global__ __launch_bounds__(256) void k_net_fwd(const uint16_t* __restrict__ x, const bf16x4* __restrict__ fw,
                                                  uint16_t* __restrict__ h1g, uint16_t* __restrict__ h2g,
                                                  float* __restrict__ y, int64_t count) {
@@ -413,10 +437,14 @@ hipError_t net_inputs(const LevelArgs& L, NetDev& N, const T* r, const T* e, int
   return hipGetLastError();
 }
 
-hipError_t net_forward(NetDev& N, int64_t count, hipStream_t s) {
+hipError_t net_forward(NetDev& N, int64_t count, hipStream_t s, bool keep) {
   if (count > N.cap) return hipErrorInvalidValue;
-  k_net_fwd<<<(unsigned)((count + G - 1) / G), 256, 0, s>>>(N.x, reinterpret_cast<const bf16x4*>(N.fw), N.h1, N.h2,
-                                                            N.y, count);
+  if (keep)
+    k_net_fwd<<<(unsigned)((count + G - 1) / G), 256, 0, s>>>(N.x, reinterpret_cast<const bf16x4*>(N.fw), N.h1,
+                                                              N.h2, N.y, count);
+  else
+    k_net_infer<<<(unsigned)((count + GI - 1) / GI), 256, 0, s>>>(N.x, reinterpret_cast<const bf16x4*>(N.fw), N.y,
+                                                                  count);
   return hipGetLastError();
 }
 

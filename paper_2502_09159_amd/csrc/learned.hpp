@@ -45,8 +45,9 @@ template <typename T>
 hipError_t net_inputs(const LevelArgs& L, NetDev& N, const T* r, const T* e, int64_t first, int64_t count,
                       hipStream_t s);
 
-// Forward pass over `count` samples held in the workspace (keeps activations).
-hipError_t net_forward(NetDev& N, int64_t count, hipStream_t s);
+// Forward pass over `count` samples held in the workspace; keep: also store
+// the hidden activations (for a backward pass), else inference only.
+hipError_t net_forward(NetDev& N, int64_t count, hipStream_t s, bool keep);
 
 // Correction head: cell-local velocity corrections (times s_T) into E
 // (the Vanka scratch layout) and pressure corrections added to x.

@@ -408,7 +408,7 @@ void net_correct(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x) {
   for (int64_t first = 0; first < total; first += kNetChunk) {
     int64_t cnt = std::min<int64_t>(kNetChunk, total - first);
     HIPCHK(net_inputs<T>(D.a, c->net, r, (const T*)nullptr, first, cnt, c->stream));
-    HIPCHK(net_forward(c->net, cnt, c->stream));
+    HIPCHK(net_forward(c->net, cnt, c->stream, false));
     HIPCHK(net_correction<T>(D.a, c->net, first, cnt, D.E, x, c->stream));
   }
   HIPCHK(launch_vanka_gather_only<T>(D.a, D.E, x, T(1), c->stream));
@@ -1125,7 +1125,7 @@ stmg_status stmg_learned_train(stmg_ctx* c, const float* rp, const float* ep, in
         const int64_t pair = job / nchunk, first = (job % nchunk) * batch;
         const int64_t cnt = std::min<int64_t>(batch, per - first);
         HIPCHK(net_inputs<float>(a, c->net, rp + pair * nd, ep + pair * nd, first, cnt, c->stream));
-        HIPCHK(net_forward(c->net, cnt, c->stream));
+        HIPCHK(net_forward(c->net, cnt, c->stream, true));
         HIPCHK(net_loss(c->net, cnt, c->stream));
         HIPCHK(net_backward(c->net, cnt, c->stream));
         HIPCHK(net_adam(c->net, ++t, lr, c->stream));
@@ -1162,7 +1162,7 @@ stmg_status stmg_learned_gradient(stmg_ctx* c, int level, const double* r, const
   return (stmg_status)guarded(c, [&] {
     net_alloc(c, total);
     HIPCHK(net_inputs<double>(a, c->net, r, e, 0, total, c->stream));
-    HIPCHK(net_forward(c->net, total, c->stream));
+    HIPCHK(net_forward(c->net, total, c->stream, true));
     HIPCHK(net_loss(c->net, total, c->stream));
     HIPCHK(net_backward(c->net, total, c->stream));
     std::vector<float> g(kNetParams);
