@@ -217,8 +217,9 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
     sCX[tid] = mat_el(mat, i, sSrc[0][m][i]);
     sCY[tid] = mat_el(mat, i, sSrc[1][m][i]);
   }
+  // sPsi[(z C + l) 16 + lane16]: the lanes of a row read consecutive words (no bank conflicts)
   for (int t = tid; t < 16 * ZP * C; t += blockDim.x) {
-    const int l = t % C, z = (t / C) % ZP, ll = t / (C * ZP), px = ll & 3, py = ll >> 2;
+    const int ll = t % 16, l = (t / 16) % C, z = t / (16 * C), px = ll & 3, py = ll >> 2;
     sPsi[t] = (px < Q && py < Q) ? tpsi[(px + Q * py + Q * Q * z) * C + l] : T(0);
   }
   __syncthreads();
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
   const int W = Q * L.n;
   const int64_t NE = D == 3 ? (int64_t)W * W * W : (int64_t)W * W;
   T* Ec = E + (cc0 * Q + qx) + (int64_t)W * (cc1 * Q + qy) + (D == 3 ? (int64_t)W * W * cc2 * Q : 0);
-  const int po = lane16 * ZP * C;  // this lane's psi rows
+  const int po = lane16;  // this lane's column of the psi table
 
   // nodal values of (n, temporal dof bb, comp) interpolated to the Gauss points
   auto interp = [&](int n, int bb, int comp, T (&uq)[ZP]) {
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
           for (int z = 0; z < ZP; ++z) {
             T s = 0;
 #pragma unroll
-            for (int l = 0; l < C; ++l) s += sPsi[pr + z * C + l] * pl[l];
+            for (int l = 0; l < C; ++l) s += sPsi[pr + (z * C + l) * 16] * pl[l];
             pres[z] = s;
           }
         }
@@ -384,7 +385,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
           for (int l = 0; l < C; ++l) {
             T s = 0;
 #pragma unroll
-            for (int z = 0; z < ZP; ++z) s += sPsi[pr + z * C + l] * dv[z];
+            for (int z = 0; z < ZP; ++z) s += sPsi[pr + (z * C + l) * 16] * dv[z];
             s = row_sum16(s);
             if (lane16 == l) mine = s;
           }
