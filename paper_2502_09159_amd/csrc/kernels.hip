@@ -734,9 +734,12 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
   for (int it = 0; it < TPW; ++it) {
     const int t = wave + it * 4;
     T (&cur)[NKB][4] = fa[DB ? (it & 1) : 0];
+    // tile loads are unconditional (clamped tile index): a load under a branch
+    // makes the compiler wait for it even where it was not issued, and the
+    // MFMAs of this tile would wait for the next tile's loads
+    if (!DB && it > 0) load_tile(min(t, NKB - 1), cur);
+    if (DB && it + 1 < TPW) load_tile(min(t + 4, NKB - 1), fa[(it + 1) & 1]);
     if (t < NKB) {
-      if (!DB && it > 0) load_tile(t, cur);
-      if (DB && it + 1 < TPW && t + 4 < NKB) load_tile(t + 4, fa[(it + 1) & 1]);
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) acc[it][ct] = v4{0, 0, 0, 0};
 #pragma unroll
