@@ -422,10 +422,10 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
 //   KIND 0 (operator): y = sum (mode 0) or b - sum (mode 1); Dirichlet rows identity
 //   KIND 1 (smoother): x += omega / valence * sum; Dirichlet nodes unchanged
 //                      (mode 1: x starts at 0, so x = omega / valence * sum and 0)
-template <typename T, int D, int QQ, int KIND>
+template <typename T, int D, int QQ, int KIND, int mode>
 __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __restrict__ E, const T* __restrict__ xin,
-                                                     const T* __restrict__ b, T* __restrict__ out, int mode,
-                                                     T omega, int lxw) {
+                                                     const T* __restrict__ b, T* __restrict__ out, T omega,
+                                                     int lxw) {
   constexpr int q = QQ - 1;
   const int c = (blockIdx.x << lxw) + (int)(threadIdx.x & ((1 << lxw) - 1));
   const int rows = 256 >> lxw, nyb = (L.nn + rows - 1) / rows;
@@ -461,42 +461,84 @@ __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __res
   const T* Ef = E + field * NE;
   const int ny = (gy % q == 0) ? 2 : 1, nz = D == 3 ? ((gz % q == 0) ? 2 : 1) : 1;
   const int dy = gy + gy / q, dz = gz + gz / q;
+  // the values the outputs need, read first (node q of the row start belongs
+  // to the next thread unless this is the last one: read anyway)
+  T bv[q + 1], xv[q + 1];
+#pragma unroll
+  for (int j = 0; j < q + 1; ++j) {
+    const int64_t id = row0 + g0 + j;
+    if (KIND == 0 && mode) bv[j] = b[id];
+    if (KIND == 1 && !mode) xv[j] = out[id];
+  }
+  // Dirichlet nodes of the row (x = 0 and x = 1): the operator copies x there
+  const T xd0 = KIND == 0 ? xin[row0] : T(0), xd1 = KIND == 0 ? xin[row0 + L.nn - 1] : T(0);
+  // the copies of the thread's nodes, summed in a fixed order (u, v): own
+  // cell, then the cell below along x.  In the grid layout every copy is read
+  // unconditionally (one a node does not have is read from its own row and
+  // weighted out), so that all loads are in flight together (a load under a
+  // branch makes the compiler wait for it); in the cell-major layout such
+  // extra reads would each touch a line per lane, so only the needed ones are made.
   T own[q], below = T(0);
 #pragma unroll
   for (int j = 0; j < q; ++j) own[j] = T(0);
-  // fixed order (u, v), own cell then the cell below along x
-#pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    if (u >= nz) break;
-#pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      if (v >= ny) break;
-      // the x-row (duplicated y index dy - v, z index dz - u) of cell c; er[-1]
-      // is the last node of the row in cell c - 1
-      const T* er;
-      if constexpr (CM) {
-        const int DY = dy - v, DZ = D == 3 ? dz - u : 0;
-        const int64_t cellc = c + (int64_t)L.n * ((DY / QQ) + (D == 3 ? (int64_t)L.n * (DZ / QQ) : 0));
-        er = Ef + cellc * NLQ + ((D == 3 ? (DZ % QQ) * QQ : 0) + DY % QQ) * QQ;
-      } else {
-        er = Ef + (D == 3 ? (int64_t)(dz - u) * W * W : 0) + (int64_t)(dy - v) * W + (int64_t)QQ * c;
-      }
-      const T* el = CM ? er - NLQ + QQ : er;  // el[-1]: last node of the row in cell c - 1
-      T ev[q];
-      if constexpr (QQ == 4 && sizeof(T) == 4) {  // 16-byte aligned
-        const float4 t4 = *reinterpret_cast<const float4*>(er);
-        ev[0] = t4.x; ev[1] = t4.y; ev[2] = t4.z;
-      } else if constexpr (QQ == 4) {
-        const double2 t0 = *reinterpret_cast<const double2*>(er);
-        ev[0] = t0.x; ev[1] = t0.y; ev[2] = er[2];
-      } else {
-#pragma unroll
-        for (int j = 0; j < q; ++j) ev[j] = er[j];
-      }
-#pragma unroll
-      for (int j = 0; j < q; ++j) own[j] += ev[j];
-      if (c > 0) below += el[-1];
+  auto row_ptr = [&](int uu, int vv) -> const T* {  // x-row (dy - vv, dz - uu) of cell c
+    if constexpr (CM) {
+      const int DY = dy - vv, DZ = D == 3 ? dz - uu : 0;
+      const int64_t cellc = c + (int64_t)L.n * ((DY / QQ) + (D == 3 ? (int64_t)L.n * (DZ / QQ) : 0));
+      return Ef + cellc * NLQ + ((D == 3 ? (DZ % QQ) * QQ : 0) + DY % QQ) * QQ;
+    } else {
+      return Ef + (D == 3 ? (int64_t)(dz - uu) * W * W : 0) + (int64_t)(dy - vv) * W + (int64_t)QQ * c;
     }
+  };
+  auto read_row = [&](const T* er, T (&ev)[q]) {
+    if constexpr (QQ == 4 && sizeof(T) == 4) {  // 16-byte aligned
+      const float4 t4 = *reinterpret_cast<const float4*>(er);
+      ev[0] = t4.x; ev[1] = t4.y; ev[2] = t4.z;
+    } else if constexpr (QQ == 4) {
+      const double2 t0 = *reinterpret_cast<const double2*>(er);
+      ev[0] = t0.x; ev[1] = t0.y; ev[2] = er[2];
+    } else {
+#pragma unroll
+      for (int j = 0; j < q; ++j) ev[j] = er[j];
+    }
+  };
+  // el - 1: the last node of the row in cell c - 1
+  auto left_ptr = [&](const T* er) -> const T* { return CM ? er - NLQ + QQ - 1 : er - 1; };
+  if constexpr (CM) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (u >= nz) break;
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        if (v >= ny) break;
+        const T* er = row_ptr(u, v);
+        T ev[q];
+        read_row(er, ev);
+#pragma unroll
+        for (int j = 0; j < q; ++j) own[j] += ev[j];
+        if (c > 0) below += *left_ptr(er);
+      }
+    }
+  } else {
+    T ev[2][2][q], evl[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const bool use = u < nz && v < ny;
+        const T* er = row_ptr(use ? u : 0, use ? v : 0);
+        read_row(er, ev[u][v]);
+        evl[u][v] = *(c > 0 ? left_ptr(er) : er);  // (c = 0: an in-row value, weighted out)
+      }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const bool use = u < nz && v < ny;
+#pragma unroll
+        for (int j = 0; j < q; ++j) own[j] += use ? ev[u][v][j] : T(0);
+        below += use && c > 0 ? evl[u][v] : T(0);
+      }
   }
   const T vyz = T(ny * nz);
 #pragma unroll
@@ -507,11 +549,11 @@ __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __res
     const bool dir = g == 0 || g == L.nn - 1;
     const T sj = j < q ? (j == 0 && c > 0 ? own[0] + below : own[j < q ? j : 0]) : T(0);
     if (KIND == 0) {
-      if (dir) out[id] = mode ? b[id] - xin[id] : xin[id];
-      else out[id] = mode ? b[id] - sj : sj;
+      const T v = dir ? (g == 0 ? xd0 : xd1) : sj;
+      out[id] = mode ? bv[j] - v : v;
     } else if (!dir) {
       const T val = (j == 0 && c > 0) ? vyz * T(2) : vyz;
-      out[id] = mode ? omega / val * sj : out[id] + omega / val * sj;
+      out[id] = mode ? omega / val * sj : xv[j] + omega / val * sj;
     } else if (mode) {
       out[id] = T(0);
     }
@@ -537,7 +579,10 @@ static hipError_t node_gather(const LevelArgs& L, const T* E, const T* xin, cons
 #define STMG_NG(DD, QQ)                                                                                  \
   if (L.d == DD && L.Q == QQ) {                                                                           \
     const int lxw = gather_lxw(L);                                                                      \
-    k_node_gather<T, DD, QQ, KIND><<<gather_grid<DD>(L, lxw), 256, 0, s>>>(L, E, xin, b, out, mode, omega, lxw); \
+    if (mode)                                                                                             \
+      k_node_gather<T, DD, QQ, KIND, 1><<<gather_grid<DD>(L, lxw), 256, 0, s>>>(L, E, xin, b, out, omega, lxw); \
+    else                                                                                                  \
+      k_node_gather<T, DD, QQ, KIND, 0><<<gather_grid<DD>(L, lxw), 256, 0, s>>>(L, E, xin, b, out, omega, lxw); \
     return hipGetLastError();                                                                             \
   }
   STMG_NG(2, 3) STMG_NG(2, 4) STMG_NG(3, 3) STMG_NG(3, 4)
