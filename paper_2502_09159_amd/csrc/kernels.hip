@@ -94,8 +94,8 @@ namespace {
 // rotations) or inside a row of 16 lanes (rotations by multiples of 4).  The
 // source lane of every permutation is read back on the device once per block,
 // so the contraction coefficients never depend on the rotation direction.
-constexpr int kQuadRot1 = 0x39, kQuadRot2 = 0x4E, kQuadRot3 = 0x93;
-constexpr int kRowRot1 = 0x12C, kRowRot2 = 0x128, kRowRot3 = 0x124;
+constexpr int kQuadRot1 = 0x39, kQuadRot2 = 0x4E, kQuadRot3 = 0x93;  // quad_perm [1,2,3,0], [2,3,0,1], [3,0,1,2]
+constexpr int kRowRot1 = 0x12C, kRowRot2 = 0x128, kRowRot3 = 0x124;  // row_ror 12, 8, 4
 constexpr int kQuadSwap1 = 0xB1;
 
 template <int CTRL>
@@ -117,7 +117,32 @@ __device__ __forceinline__ double dpp(double v) {
 // out = sum_m c[m] v(source lane of permutation m), along x (DIR 0) or y (DIR 1)
 template <int DIR, typename T>
 __device__ __forceinline__ T lane_contract(T v, const T* c) {
-  if constexpr (DIR == 0)
+  if constexpr (__is_same(T, float)) {
+    // FP32: one multiply and three FMAs whose first operand is read through
+    // the permutation (the compiler does not fold a permutation into an FMA,
+    // so it would spend a move on each).  The permutations are those of
+    // kQuadRot1..3 / kRowRot1..3.  The no-ops keep two wait states between a
+    // vector write of a register and a permuted read of it: v, written before
+    // the block, and the result, which a permutation after it may read.
+    float r;
+    if constexpr (DIR == 0)
+      asm("v_mul_f32 %0, %2, %1\n\ts_nop 1\n\t"
+          "v_fmac_f32_dpp %0, %1, %3 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %0, %1, %4 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %0, %1, %5 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "s_nop 1"
+          : "=&v"(r)
+          : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    else
+      asm("v_mul_f32 %0, %2, %1\n\ts_nop 1\n\t"
+          "v_fmac_f32_dpp %0, %1, %3 row_ror:12 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %0, %1, %4 row_ror:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %0, %1, %5 row_ror:4 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "s_nop 1"
+          : "=&v"(r)
+          : "v"(v), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    return r;
+  } else if constexpr (DIR == 0)
     return c[0] * v + c[1] * dpp<kQuadRot1>(v) + c[2] * dpp<kQuadRot2>(v) + c[3] * dpp<kQuadRot3>(v);
   else
     return c[0] * v + c[1] * dpp<kRowRot1>(v) + c[2] * dpp<kRowRot2>(v) + c[3] * dpp<kRowRot3>(v);
@@ -1690,8 +1715,10 @@ template hipError_t launch_dot<float>(const float*, const float*, int64_t, doubl
 // ---- Gram-Schmidt passes of the Arnoldi process (lagged CGS2), templated on
 // a bound NVM of the number of basis vectors (per-thread accumulators; the
 // basis values of one element are kept in registers for NVM <= 32 and read
-// again otherwise), kFusedBlocks blocks, sums in a fixed order.
-constexpr int kFusedBlocks = 2048;
+// again otherwise), kFusedBlocks blocks, sums in a fixed order.  Two work
+// groups per compute unit: with 13-16 basis vectors read side by side, fewer
+// streams in flight ran 4% faster than eight work groups per unit.
+constexpr int kFusedBlocks = 512;
 
 // Sums of nv values over a block, written to partial[k * kFusedBlocks + block].
 template <int NA>

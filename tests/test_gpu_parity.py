@@ -76,6 +76,28 @@ def test_smoother_every_level(name):
             assert rel(host(xg), ref) < 1e-12, (l, steps, rel(host(xg), ref))
 
 
+@pytest.mark.parametrize("name", NAMES)
+def test_fp32_smoother_every_level(name):
+    """Eq. (vanka) in the mixed precision's FP32 hierarchy: two sweeps, whose
+    second residual comes from the FP32 operator, against the FP64 oracle.
+    Bound 1e-5 relative (measured at most 2.4e-7): FP32 rounding (unit
+    roundoff 6e-8) of the operator, the stored local factors and the solves,
+    amplified by the conditioning of the cell systems."""
+    g, o = solver(name, precision=1), oracle_mg(name)
+    rng = np.random.default_rng(14)
+    for l, L in enumerate(o.levels[:-1]):
+        dm = L.dirichlet_mask()
+        b = rng.standard_normal(L.ndofs); b[dm] = 0
+        x0 = rng.standard_normal(L.ndofs); x0[dm] = 0
+        for steps in (1, 2):
+            xg = dev(x0)
+            g.smooth(dev(b), xg, steps=steps, level=l)
+            ref = o.smoothers[l].smooth(b, x0.copy(), steps, L.apply)
+            err = rel(host(xg), ref)
+            announce(f"fp32 smooth {name} level {l} steps {steps}: {err:.2e}")
+            assert err < 1e-5, (l, steps, err)
+
+
 def test_dense_and_factored_vanka_agree():
     """The dense local inverse and its Schur-factored form give the same sweep."""
     name = "c2_small"
