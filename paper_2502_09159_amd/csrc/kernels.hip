@@ -321,14 +321,22 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
 #pragma unroll 1
       for (int a = 0; a < NT; ++a) {
         const T ca = tcoef[a];
-        // pressure of dof a at the Gauss points
+        // the continuity row this lane accumulates into at the end of the step,
+        // read now (clamped to a row of this cell, so always in bounds) so that
+        // its latency overlaps the step
+        const int64_t prow = (int64_t)n * L.slab + (int64_t)NT * L.Mv + (int64_t)a * L.Mp + cell * C;
+        const T prev_in = (comp > 0 ? y : (mode ? b : y))[prow + min(lane16, C - 1)];
+        // pressure of dof a at the Gauss points (read unconditionally: cell is
+        // clamped to 0 past the last cell, and those lanes take zeros)
         T pres[ZP];
         {
-          const T* ps = x + (int64_t)n * L.slab + (int64_t)NT * L.Mv + (int64_t)a * L.Mp + cell * C +
-                        opaque_v(0);
+          const T* ps = x + prow + opaque_v(0);
           T pl[C];
 #pragma unroll
-          for (int l = 0; l < C; ++l) pl[l] = cvalid ? ps[l] : T(0);
+          for (int l = 0; l < C; ++l) {
+            const T v = ps[l];
+            pl[l] = cvalid ? v : T(0);
+          }
           const int pr = opaque_v(po);
 #pragma unroll
           for (int z = 0; z < ZP; ++z) {
@@ -415,9 +423,8 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
             if (lane16 == l) mine = s;
           }
           if (cvalid && lane16 < C) {
-            const int64_t id = (int64_t)n * L.slab + (int64_t)NT * L.Mv + (int64_t)a * L.Mp + cell * C + lane16;
-            const T prev = comp > 0 ? y[id] : (mode ? b[id] : T(0));
-            y[id] = mode ? prev - mine : prev + mine;
+            const T prev = comp > 0 || mode ? prev_in : T(0);
+            y[prow + lane16] = mode ? prev - mine : prev + mine;
           }
         }
         // rotate: uq[j] <- uq[j + 1]
