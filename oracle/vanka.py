@@ -11,6 +11,12 @@ Since Dirichlet rows and columns of S are the identity, taking ALL dofs of the
 cell (Dirichlet ones included) pads A_T with identity rows/columns; the update
 is masked to zero on Dirichlet dofs.  A_T is the same for every subinterval
 (uniform tau), so one inverse per spatial cell is stored.
+
+On a mesh of one cell the patch K x I_n holds every spatial dof of its
+subinterval, and A_T is singular exactly like the level matrix: the constant
+pressure of each temporal dof is in its kernel (Eq. (DefRsSs)).  Such a patch
+is solved in the mean-zero pressure space, bordered with the constraint
+<p_a, M_h^p c_1> = 0 per temporal dof as the coarse solve is (reading G6).
 """
 import numpy as np
 
@@ -66,6 +72,23 @@ def local_matrices_factored(L: SpaceTimeLevel, cells=None):
     return np.array(out)
 
 
+def bordered_inverse(L: SpaceTimeLevel, A):
+    """Inverse of the whole-domain patch matrices A (one cell) in the mean-zero
+    pressure space: the top-left block of [[A, Z], [Z^T, 0]]^{-1}, Z holding
+    the cell's pressure moments at the pressure slots of each temporal dof."""
+    s = L.sp
+    b = A.shape[1]
+    p0 = L.nt * s.d * s.nloc                      # first pressure slot
+    Z = np.zeros((b, L.nt))
+    for a in range(L.nt):
+        Z[p0 + a * s.C:p0 + (a + 1) * s.C, a] = s.mom_glob
+    out = np.empty_like(A)
+    for c in range(A.shape[0]):
+        Ab = np.block([[A[c], Z], [Z.T, np.zeros((L.nt, L.nt))]])
+        out[c] = np.linalg.inv(Ab)[:b, :b]
+    return out
+
+
 class Vanka:
     def __init__(self, L: SpaceTimeLevel, omega, literal=None):
         self.L = L
@@ -73,7 +96,7 @@ class Vanka:
         if literal is None:
             literal = L.ndofs <= 200_000
         A = local_matrices_literal(L) if literal else local_matrices_factored(L)
-        self.inv = np.linalg.inv(A)
+        self.inv = bordered_inverse(L, A) if L.sp.mesh.n_cells == 1 else np.linalg.inv(A)
         self.idx = [cell_dofs(L, n) for n in range(L.N)]
         # valence D: number of spatial cells sharing the dof (pressure: 1)
         val = np.zeros(L.ndofs)
