@@ -111,6 +111,21 @@ stmg_status stmg_setup(const stmg_params* p, stmg_ctx** out);
 stmg_status stmg_destroy(stmg_ctx* ctx);
 const char* stmg_last_error(const stmg_ctx* ctx);
 
+/* Execution options, for tests and tuning (they change the work split, not
+ * the result beyond rounding order):
+ *  STMG_OPT_APPLY_SUBINTERVALS: subintervals of a cell that one wave of the
+ *    operator's cell kernel walks through, carrying the jump term of Eq.
+ *    (InAlg) in registers (0 = automatic: all N unless the grid would not
+ *    fill the chip; values are clamped to [1, N]);
+ *  STMG_OPT_NET_CHUNK: space-time cells per inference chunk of the learned
+ *    correction (0 = default 65536; at most 65536).
+ * Returns STMG_EINVAL for an unknown option or a negative value. */
+typedef enum {
+  STMG_OPT_APPLY_SUBINTERVALS = 1,
+  STMG_OPT_NET_CHUNK = 2
+} stmg_option;
+stmg_status stmg_set_option(stmg_ctx* ctx, int option, int64_t value);
+
 /* Record per-phase device times (smoother, rest of the V-cycle, outer
  * operator applies, other) in stmg_solve_info; adds event overhead. */
 stmg_status stmg_set_phase_timing(stmg_ctx* ctx, int on);
@@ -122,6 +137,12 @@ stmg_status stmg_sizes(const stmg_ctx* ctx, int level, int64_t* n_dofs, int64_t*
 
 /* y = S_level x (Eq. (GloSys) on that level), FP64.  x and y must not alias. */
 stmg_status stmg_apply_operator(stmg_ctx* ctx, int level, const double* x, double* y);
+
+/* y = S_level x evaluated in the V-cycle's precision: in a mixed context x
+ * is rounded to FP32, the FP32 operator of the V-cycle is applied and y is
+ * widened back to FP64; in an FP64 context this equals stmg_apply_operator.
+ * x and y are FP64 device vectors and must not alias. */
+stmg_status stmg_apply_operator_vcycle_precision(stmg_ctx* ctx, int level, const double* x, double* y);
 
 /* r = b - S_level x, FP64. */
 stmg_status stmg_residual(stmg_ctx* ctx, int level, const double* b, const double* x, double* r);

@@ -209,3 +209,53 @@ class SampledLevel:
             z = self.local_solve(c, n, r)
             s += z[(a * self.d + comp) * self.nloc + i]
         return s / len(owners)
+
+    # ------------------------------------------------------ learned correction
+    def learned_cell_tensor(self, r, T, n):
+        """The 15 x 27 input tensor of space-time cell (T, n) as
+        `learned.cell_tensors` builds it (3D Q2/P1 x DG(1) levels), unscaled,
+        and the cell's Dirichlet mask."""
+        if self.d != 3 or self.r != 1 or self.k != 1:
+            raise ValueError("the learned correction acts on 3D Q2/P1 x DG(1) levels")
+        cn = self.cell_nodes(T)
+        mask = np.array([self.is_boundary(h) for h in cn], dtype=float)
+        X = np.zeros((15, 27))
+        for a in range(2):
+            for comp in range(3):
+                X[comp * 2 + a] = r[[self.v_dof(n, a, comp, h) for h in cn]] * (1.0 - mask)
+            for l in range(4):
+                X[6 + 4 * a + l] = r[self.p_dof(n, a, T, l)]
+        X[14] = mask
+        return X, mask
+
+    def learned_cell_output(self, Ws, r, T, n):
+        """s_T head(net(R_T r / s_T)) of one space-time cell: velocity (6, 27)
+        and pressure (8,), with the network and head of `learned`."""
+        from . import learned as ln
+        if not hasattr(self, "_net"):
+            self._net = {}
+        if (T, n) not in self._net:
+            X, mask = self.learned_cell_tensor(r, T, n)
+            s = float(np.sqrt(np.sum(X[:6] ** 2) + np.sum(X[6:14, 0] ** 2)))
+            if s == 0.0:
+                self._net[(T, n)] = (np.zeros((6, 27)), np.zeros(8))
+            else:
+                Xn = X.copy()
+                Xn[:14] /= s
+                vel, pre = ln.head(ln.forward(Ws, Xn[None]), mask[None])
+                self._net[(T, n)] = (vel[0] * s, pre[0] * s)
+        return self._net[(T, n)]
+
+    def learned_correction_entry(self, Ws, r, idx):
+        """[sum_T R_T^T s_T head(net(R_T r / s_T))][idx], velocity divided by
+        the valence, zero on Dirichlet rows (`learned.correction`).  The
+        per-cell outputs are cached: one r per SampledLevel."""
+        kind, n, a, u, v = self.decode(idx)
+        if kind == "p":
+            return self.learned_cell_output(Ws, r, u, n)[1][4 * a + v]
+        comp, g = u, v
+        if self.is_boundary(g):
+            return 0.0
+        owners = self.cells_of_node(g)
+        s = sum(self.learned_cell_output(Ws, r, c, n)[0][comp * 2 + a, i] for c, i in owners)
+        return s / len(owners)

@@ -18,7 +18,7 @@ FLAGS = [
 
 def build(verbose=True):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(SRC, "_build", src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
@@ -26,8 +26,14 @@ def build(verbose=True):
         cmd.remove("-shared")
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append(cmd)
         objs.append(obj)
+    # the sources compile independently: run them side by side
+    procs = [subprocess.Popen(c) for c in cmds]
+    codes = [p.wait() for p in procs]
+    for c, rc in zip(cmds, codes):
+        if rc != 0:
+            raise subprocess.CalledProcessError(rc, c)
     tmp = LIB + ".tmp"
     cmd = [hipcc] + FLAGS + objs + ["-o", tmp, "-Wl,-rpath,/opt/rocm/lib:/opt/rocm/llvm/lib"]
     if verbose:

@@ -634,13 +634,14 @@ static hipError_t node_gather(const LevelArgs& L, const T* E, const T* xin, cons
 
 template <typename T, int D, int Q, int NT>
 static hipError_t apply_impl(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y,
-                             int mode, T* E, hipStream_t s, bool gather) {
+                             int mode, T* E, hipStream_t s, bool gather, int nper_req) {
   constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
   if (L.C != C || L.nt != NT || L.Q != Q || L.nodes >= (int64_t(1) << 31)) return hipErrorInvalidValue;
   const int64_t ncells = L.Mp / L.C;
   const int64_t nbx = (ncells + 15) / 16;
   // split the subintervals into chunks when there are too few cells to fill the chip
   int64_t nchunk = std::min<int64_t>(L.N, std::max<int64_t>(1, (4096 + 4 * nbx - 1) / (4 * nbx)));
+  if (nper_req > 0) nchunk = (L.N + std::min(nper_req, L.N) - 1) / std::min(nper_req, L.N);
   const int nper = (int)((L.N + nchunk - 1) / nchunk);
   nchunk = (L.N + nper - 1) / nper;
   k_apply<T, D, Q, NT><<<dim3((unsigned)nbx, (unsigned)nchunk), 256, 0, s>>>(L, geo, tab, x, b, y, E, mode, nper);
@@ -651,9 +652,9 @@ static hipError_t apply_impl(const LevelArgs& L, const T* geo, const T* tab, con
 
 template <typename T>
 hipError_t launch_apply(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y, int mode,
-                        T* E, hipStream_t s, bool gather) {
+                        T* E, hipStream_t s, bool gather, int nper) {
 #define STMG_AP(DD, QQ, NN) \
-  if (L.d == DD && L.Q == QQ && L.nt == NN) return apply_impl<T, DD, QQ, NN>(L, geo, tab, x, b, y, mode, E, s, gather);
+  if (L.d == DD && L.Q == QQ && L.nt == NN) return apply_impl<T, DD, QQ, NN>(L, geo, tab, x, b, y, mode, E, s, gather, nper);
   STMG_AP(2, 3, 1) STMG_AP(2, 3, 2) STMG_AP(2, 3, 3) STMG_AP(2, 3, 4)
   STMG_AP(2, 4, 1) STMG_AP(2, 4, 2) STMG_AP(2, 4, 3) STMG_AP(2, 4, 4)
   STMG_AP(3, 3, 1) STMG_AP(3, 3, 2) STMG_AP(3, 3, 3) STMG_AP(3, 3, 4)
@@ -1983,7 +1984,7 @@ hipError_t launch_project_pressure(const LevelArgs& L, const double* mom, double
 // explicit instantiations
 #define STMG_INST(T)                                                                                                \
   template hipError_t launch_apply<T>(const LevelArgs&, const T*, const T*, const T*, const T*, T*, int, T*,      \
-                                      hipStream_t, bool);                                                           \
+                                      hipStream_t, bool, int);                                                      \
   template hipError_t launch_vanka_factored<T>(const LevelArgs&, const T*, const T*, const T*, const T*, const T*, \
                                                const T*, T*, T, T*, hipStream_t, bool, bool);                       \
   template hipError_t launch_vanka_dense<T>(const LevelArgs&, const T*, const T*, T*, T, hipStream_t);             \

@@ -39,8 +39,10 @@ inline int table_size(int Q, int nt, int nloc, int C) { return 2 * Q * Q + 2 * Q
 template <typename T>
 // gather = false runs the cell kernel only (E written, y's pressure rows
 // written, velocity rows untouched): for timing.
+// nper > 0 fixes the subintervals one wave walks through (clamped to [1, N]);
+// 0 picks them so that the grid fills the chip.
 hipError_t launch_apply(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y, int mode,
-                        T* E, hipStream_t s, bool gather = true);
+                        T* E, hipStream_t s, bool gather = true, int nper = 0);
 
 // Vanka correction with factored local inverses: x += omega D^-1 sum R^T A^-1 R r.
 // Asw: A_s^{-1} of every cell in MFMA operand order (see vanka_swizzle_index),

@@ -160,6 +160,9 @@ struct stmg_ctx {
   bool net_ready = false, learned_on = false, learned_disabled = false;
   int learned_reading = 1;  // 1: every level reaching a Q2/P1 x DG(1) level on its mesh; 2: those levels only
   std::vector<void*> lsave;  // per level: copy of x before a correction
+  // execution options (stmg_set_option)
+  int opt_apply_nper = 0;      // subintervals per wave of the operator's cell kernel (0: automatic)
+  int64_t opt_net_chunk = 0;   // space-time cells per inference chunk (0: the default)
 };
 
 namespace {
@@ -294,7 +297,7 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
 // ------------------------------------------------------------- level ops
 template <typename T>
 void op_apply(stmg_ctx* c, DevLevel<T>& D, const T* x, const T* b, T* y, int mode) {
-  HIPCHK(launch_apply<T>(D.a, D.geo, D.tab, x, b, y, mode, D.E, c->stream));
+  HIPCHK(launch_apply<T>(D.a, D.geo, D.tab, x, b, y, mode, D.E, c->stream, true, c->opt_apply_nper));
 }
 
 template <typename T>
@@ -405,8 +408,9 @@ Hier<float>& hier_of<float>(stmg_ctx* c) { return c->H32; }
 template <typename T>
 void net_correct(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x) {
   const int64_t total = (int64_t)D.a.N * (D.a.Mp / D.a.C);
-  for (int64_t first = 0; first < total; first += kNetChunk) {
-    int64_t cnt = std::min<int64_t>(kNetChunk, total - first);
+  const int64_t chunk = c->opt_net_chunk > 0 ? std::min<int64_t>(c->opt_net_chunk, kNetChunk) : kNetChunk;
+  for (int64_t first = 0; first < total; first += chunk) {
+    int64_t cnt = std::min<int64_t>(chunk, total - first);
     HIPCHK(net_inputs<T>(D.a, c->net, r, (const T*)nullptr, first, cnt, c->stream));
     HIPCHK(net_forward(c->net, cnt, c->stream, false));
     HIPCHK(net_correction<T>(D.a, c->net, first, cnt, D.E, x, c->stream));
@@ -731,6 +735,33 @@ stmg_status stmg_apply_operator(stmg_ctx* c, int level, const double* x, double*
     op_apply<double>(c, c->H64.L[level], x, x, y, 0);
     HIPCHK(hipStreamSynchronize(c->stream));
   });
+}
+
+stmg_status stmg_apply_operator_vcycle_precision(stmg_ctx* c, int level, const double* x, double* y) {
+  if (!c || !x || !y || level < 0 || level >= (int)c->host.size()) return STMG_EINVAL;
+  return (stmg_status)per_op(
+      c, [&] { op_apply<double>(c, c->H64.L[level], x, x, y, 0); },
+      [&] {
+        DevLevel<float>& D = c->H32.L[level];
+        HIPCHK(launch_cast_d2f(x, D.x, D.ndofs, c->stream));
+        op_apply<float>(c, D, D.x, D.x, D.r, 0);
+        HIPCHK(launch_cast_f2d(D.r, y, D.ndofs, c->stream));
+      });
+}
+
+stmg_status stmg_set_option(stmg_ctx* c, int option, int64_t value) {
+  if (!c || value < 0) return STMG_EINVAL;
+  switch (option) {
+    case STMG_OPT_APPLY_SUBINTERVALS:
+      c->opt_apply_nper = (int)std::min<int64_t>(value, 1 << 20);
+      return STMG_OK;
+    case STMG_OPT_NET_CHUNK:
+      c->opt_net_chunk = value;
+      return STMG_OK;
+    default:
+      c->err = "unknown option";
+      return STMG_EINVAL;
+  }
 }
 
 stmg_status stmg_residual(stmg_ctx* c, int level, const double* b, const double* x, double* r) {

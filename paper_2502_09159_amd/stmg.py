@@ -19,6 +19,7 @@ lib = ctypes.CDLL(LIB_PATH)
 STATUS = {0: "STMG_OK", -1: "STMG_EINVAL", -2: "STMG_ENOMEM", -3: "STMG_EDEVICE", -4: "STMG_ENOCONV",
           -5: "STMG_ESINGULAR", -6: "STMG_EUNSUPPORTED"}
 FP64, MIXED_FP32 = 0, 1
+OPT_APPLY_SUBINTERVALS, OPT_NET_CHUNK = 1, 2  # stmg_option
 VANKA_FACTORED, VANKA_DENSE = 0, 1
 
 NU_FN = ctypes.CFUNCTYPE(None, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -55,6 +56,8 @@ _sig = {
     "stmg_sizes": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)],
     "stmg_apply_operator": [_P, ctypes.c_int, _P, _P],
+    "stmg_apply_operator_vcycle_precision": [_P, ctypes.c_int, _P, _P],
+    "stmg_set_option": [_P, ctypes.c_int, ctypes.c_int64],
     "stmg_residual": [_P, ctypes.c_int, _P, _P, _P],
     "stmg_smooth": [_P, ctypes.c_int, _P, _P, ctypes.c_int],
     "stmg_vanka_correction": [_P, ctypes.c_int, _P, _P],
@@ -180,6 +183,14 @@ class Solver:
     def apply(self, x, y, level=0):
         n = self.ndofs(level)
         _check(lib.stmg_apply_operator(self.ctx, level, _ptr(x, n), _ptr(y, n)), self.ctx)
+
+    def apply_vcycle_precision(self, x, y, level=0):
+        """y = S x with the operator of the V-cycle (FP32 in a mixed context)."""
+        n = self.ndofs(level)
+        _check(lib.stmg_apply_operator_vcycle_precision(self.ctx, level, _ptr(x, n), _ptr(y, n)), self.ctx)
+
+    def set_option(self, option, value):
+        _check(lib.stmg_set_option(self.ctx, int(option), int(value)), self.ctx)
 
     def residual(self, b, x, r, level=0):
         n = self.ndofs(level)

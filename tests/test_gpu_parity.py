@@ -130,6 +130,39 @@ def test_transfers_every_pair(name):
         assert rel(host(bc), P.T @ rf) < 1e-12
 
 
+SPLIT_NAMES = [n for n in NAMES if CONFIGS[n]["n_sub"] > 1]
+
+
+@pytest.mark.parametrize("name", SPLIT_NAMES)
+def test_apply_subinterval_split(name):
+    """The operator's cell kernel with every split of the slab among waves:
+    one subinterval per wave (the jump term of Eq. (InAlg) read from the
+    previous subinterval's nodes) up to all N subintervals walked by one wave
+    (the jump term carried in registers), in FP64 (1e-12) and in the FP32
+    V-cycle precision (1e-5 of the largest row; unit roundoff 6e-8)."""
+    g64, g32, o = solver(name), solver(name, precision=1), oracle_mg(name)
+    rng = np.random.default_rng(12)
+    try:
+        for l, L in enumerate(o.levels):
+            x = rng.standard_normal(L.ndofs)
+            ref = L.csr() @ x
+            N = L.N
+            for nper in sorted({1, 2, N} & set(range(1, N + 1))):
+                y = torch.empty(L.ndofs, dtype=torch.float64, device="cuda")
+                g64.set_option(1, nper)
+                g64.apply(dev(x), y, level=l)
+                e64 = rel(host(y), ref)
+                g32.set_option(1, nper)
+                g32.apply_vcycle_precision(dev(x), y, level=l)
+                e32 = rel(host(y), ref)
+                announce(f"split {name} level {l} N={N} nper={nper}: fp64 {e64:.2e} fp32 {e32:.2e}")
+                assert e64 < 1e-12
+                assert e32 < 1e-5
+    finally:
+        g64.set_option(1, 0)
+        g32.set_option(1, 0)
+
+
 @pytest.mark.parametrize("name", NAMES)
 def test_coarse_solve(name):
     """Alg. 1 step 3: bordered direct solve, mean-zero pressure."""
@@ -139,7 +172,9 @@ def test_coarse_solve(name):
     b = rng.standard_normal(L.ndofs)
     x = torch.empty(L.ndofs, dtype=torch.float64, device="cuda")
     g.coarse_solve(dev(b), x)
-    assert rel(host(x), o.coarse.solve(b)) < 1e-11
+    err = rel(host(x), o.coarse.solve(b))
+    announce(f"coarse {name}: {err:.2e}")
+    assert err < 1e-12
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -149,7 +184,9 @@ def test_vcycle(name):
     b = rhs(CONFIGS[name], 21)
     x = torch.empty(len(b), dtype=torch.float64, device="cuda")
     g.vcycle(dev(b), x)
-    assert rel(host(x), o.vcycle(b)) < 1e-11
+    err = rel(host(x), o.vcycle(b))
+    announce(f"vcycle {name}: {err:.2e}")
+    assert err < 1e-12
 
 
 @pytest.mark.parametrize("name", NAMES)

@@ -51,3 +51,19 @@ def test_sampled_correction_equals_the_vanka_correction(c):
     rows = rng.choice(L.ndofs, 120, replace=False)
     us = np.array([S.correction_entry(r, i) for i in rows])
     assert np.max(np.abs(us - u[rows])) <= 1e-10 * np.max(np.abs(u))
+
+
+def test_sampled_learned_correction_equals_the_oracle_network():
+    """learned_correction_entry (per cell, used at full size) against
+    learned.correction over the whole level (reading G15: valence-weighted
+    scatter of every cell's scaled network output, pressure per cell)."""
+    from oracle import learned as ln
+    L = SpaceTimeLevel(SpatialLevel(3, 3, 1, 0.03, 1.0), 1, 2, 0.05)
+    S = SampledLevel(3, 3, 1, 1, 2, 0.05, 0.03, 1.0)
+    W = ln.init_weights(3)
+    rng = np.random.default_rng(6)
+    r = rng.standard_normal(L.ndofs)
+    u = ln.correction(L, W, r)
+    rows = np.arange(L.ndofs)
+    us = np.array([S.learned_correction_entry(W, r, i) for i in rows])
+    assert np.max(np.abs(us - u)) <= 1e-13 * np.max(np.abs(u))
