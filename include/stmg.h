@@ -156,6 +156,22 @@ stmg_status stmg_smooth(stmg_ctx* ctx, int level, const double* b, double* x, in
  * the context's precision (inputs cast when the context is mixed). */
 stmg_status stmg_vanka_correction(stmg_ctx* ctx, int level, const double* r, double* x);
 
+/* Allocation-free variant of stmg_vanka_correction, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same correction, bit for bit, but the
+ * smoother's scratch (the cell-local velocity corrections and, in a mixed
+ * context, the FP32 copies of r and x) comes from a fixed device buffer of
+ * STMG_NOALLOC_SCRATCH_BYTES bytes that the library holds on every GPU it
+ * runs on until the process ends.  The call allocates nothing (the context
+ * must exist already).  Returns STMG_EINVAL, with a message naming the size,
+ * if the level needs more scratch than the buffer holds (about 64^3-node
+ * levels of Q3 x DG(1) with 8 subintervals in FP32 need more).  Every call on
+ * one GPU uses the same buffer: calls that overlap in time on one GPU (other
+ * host threads or streams, any context) race, and the caller must serialise
+ * them. */
+#define STMG_NOALLOC_SCRATCH_BYTES (64u << 20)
+stmg_status stmg_vanka_correction_noalloc(stmg_ctx* ctx, int level, const double* r, double* x);
+
 /* Benchmark helper: run one kernel class `reps` times back to back on the
  * level's internal work vectors, in the context's precision (the V-cycle's),
  * on the context's stream, and return the mean device time of one

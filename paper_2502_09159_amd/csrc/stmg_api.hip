@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -300,16 +301,23 @@ void op_apply(stmg_ctx* c, DevLevel<T>& D, const T* x, const T* b, T* y, int mod
   HIPCHK(launch_apply<T>(D.a, D.geo, D.tab, x, b, y, mode, D.E, c->stream, true, c->opt_apply_nper));
 }
 
+// E: the cell-local scratch of the velocity corrections (the level's own, or
+// the allocation-free entry point's)
 template <typename T>
-void op_vanka(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x, bool xzero = false) {
+void op_vanka_with(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x, T* E, bool xzero) {
   // xzero: x holds no values yet and starts at 0
   T om = (T)c->p.omega;
   if (c->p.vanka_mode == STMG_VANKA_DENSE) {
     if (xzero) HIPCHK(launch_fill<T>(x, T(0), D.ndofs, c->stream));
     HIPCHK(launch_vanka_dense<T>(D.a, D.dense, r, x, om, c->stream));
   } else {
-    HIPCHK(launch_vanka_factored<T>(D.a, D.Asw, D.Bm, D.F, D.Hinv, D.coef, r, x, om, D.E, c->stream, true, xzero));
+    HIPCHK(launch_vanka_factored<T>(D.a, D.Asw, D.Bm, D.F, D.Hinv, D.coef, r, x, om, E, c->stream, true, xzero));
   }
+}
+
+template <typename T>
+void op_vanka(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x, bool xzero = false) {
+  op_vanka_with<T>(c, D, r, x, D.E, xzero);
 }
 
 template <typename T>
@@ -796,6 +804,60 @@ stmg_status stmg_vanka_correction(stmg_ctx* c, int level, const double* r, doubl
         op_vanka<float>(c, D, D.r, D.x);
         HIPCHK(launch_cast_f2d(D.x, x, D.ndofs, c->stream));
       });
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free Vanka correction.  Its scratch lives in one fixed device
+// array per GPU (each device holds its own copy of this module variable).
+// Host code never passes the array's name to a kernel or a copy: it uses the
+// device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[STMG_NOALLOC_SCRATCH_BYTES];
+
+static unsigned char* scratch_address(int device) {
+  static std::mutex m;
+  static std::vector<unsigned char*> addr;
+  std::lock_guard<std::mutex> g(m);
+  if (device < 0) throw Error(STMG_EINVAL, "bad device ordinal");
+  if ((size_t)device >= addr.size()) addr.resize((size_t)device + 1, nullptr);
+  if (!addr[device]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));  // the current device's copy
+    if (!p) throw DeviceError("hipGetSymbolAddress returned a null address");
+    addr[device] = static_cast<unsigned char*>(p);
+  }
+  return addr[device];
+}
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+stmg_status stmg_vanka_correction_noalloc(stmg_ctx* c, int level, const double* r, double* x) {
+  if (!c || !r || !x || level < 0 || level + 1 >= (int)c->host.size()) return STMG_EINVAL;
+  const LevelHost& L = c->host[level];
+  const size_t elem = c->mixed ? sizeof(float) : sizeof(double);
+  const size_t e_bytes = align256((size_t)L.ncells * L.d * L.nt * L.nloc * L.N * elem);
+  const size_t v_bytes = c->mixed ? align256((size_t)L.ndofs * sizeof(float)) : 0;
+  const size_t need = e_bytes + 2 * v_bytes;
+  if (need > (size_t)STMG_NOALLOC_SCRATCH_BYTES)
+    return (stmg_status)fail(c, STMG_EINVAL,
+                             "level " + std::to_string(level) + " needs " + std::to_string(need) +
+                                 " bytes of smoother scratch; the allocation-free correction holds " +
+                                 std::to_string((size_t)STMG_NOALLOC_SCRATCH_BYTES));
+  return (stmg_status)guarded(c, [&] {
+    unsigned char* base = scratch_address(c->p.device);  // device is current (guarded)
+    if (c->mixed) {
+      DevLevel<float>& D = c->H32.L[level];
+      float* E = reinterpret_cast<float*>(base);
+      float* r32 = reinterpret_cast<float*>(base + e_bytes);
+      float* x32 = reinterpret_cast<float*>(base + e_bytes + v_bytes);
+      HIPCHK(launch_cast_d2f(r, r32, D.ndofs, c->stream));
+      HIPCHK(launch_cast_d2f(x, x32, D.ndofs, c->stream));
+      op_vanka_with<float>(c, D, r32, x32, E, false);
+      HIPCHK(launch_cast_f2d(x32, x, D.ndofs, c->stream));
+    } else {
+      op_vanka_with<double>(c, c->H64.L[level], r, x, reinterpret_cast<double*>(base), false);
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
 }
 
 stmg_status stmg_kernel_time(stmg_ctx* c, int which, int level, int reps, double* avg_ms) {

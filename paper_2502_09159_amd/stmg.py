@@ -61,6 +61,7 @@ _sig = {
     "stmg_residual": [_P, ctypes.c_int, _P, _P, _P],
     "stmg_smooth": [_P, ctypes.c_int, _P, _P, ctypes.c_int],
     "stmg_vanka_correction": [_P, ctypes.c_int, _P, _P],
+    "stmg_vanka_correction_noalloc": [_P, ctypes.c_int, _P, _P],
     "stmg_kernel_time": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
     "stmg_restrict": [_P, ctypes.c_int, _P, _P],
     "stmg_prolongate": [_P, ctypes.c_int, _P, _P],
@@ -203,6 +204,11 @@ class Solver:
     def vanka_correction(self, r, x, level=0):
         n = self.ndofs(level)
         _check(lib.stmg_vanka_correction(self.ctx, level, _ptr(r, n), _ptr(x, n)), self.ctx)
+
+    def vanka_correction_noalloc(self, r, x, level=0):
+        """stmg_vanka_correction with the library's fixed scratch buffer (no allocation)."""
+        n = self.ndofs(level)
+        _check(lib.stmg_vanka_correction_noalloc(self.ctx, level, _ptr(r, n), _ptr(x, n)), self.ctx)
 
     def kernel_time(self, which, level=0, reps=10):
         """Mean device time (ms) of one application of kernel class `which` on
