@@ -60,8 +60,25 @@ typedef enum {
 
 typedef enum {
   STMG_VANKA_FACTORED = 0, /* local inverse applied in Schur-factored form */
-  STMG_VANKA_DENSE = 1     /* local inverse stored as one dense b x b block */
+  STMG_VANKA_DENSE = 1,    /* local inverse stored as one dense b x b block */
+  STMG_VANKA_DECOUPLED = 2, /* the same local inverse, decoupled in time: one
+                               spatial Stokes block per eigenvalue of the
+                               temporal matrix */
+  STMG_VANKA_AUTO = 3       /* per level, the faster of the two factored forms
+                               on MI355X: decoupled on levels with at least 64
+                               velocity nodes per cell, Schur-factored below
+                               (default) */
 } stmg_vanka_mode;
+
+typedef enum {
+  STMG_LOCAL_EXACT = 0,   /* the exact patch inverse of Eq. (vanka0) (default) */
+  STMG_LOCAL_DIAGONAL = 1 /* diagonal Vanka, a cheaper smoother (the conclusion
+                             of the paper asks for cheaper local solves): the
+                             patch matrix with its spatial mass and stiffness
+                             blocks replaced by their diagonals, the temporal
+                             coupling and the divergence kept exact; applied
+                             in the decoupled form (vanka_mode is ignored) */
+} stmg_local_solver;
 
 /* nu(x) callback: evaluate the viscosity at npts physical points xyz
  * (npts x dim, row-major) into nu_out (npts).  Called on the host during
@@ -88,13 +105,14 @@ typedef struct {
   double omega;          /* Vanka relaxation */
   int precision;         /* stmg_precision */
   int vanka_mode;        /* stmg_vanka_mode */
+  int local_solver;      /* stmg_local_solver */
   int device;            /* HIP device ordinal */
   void* stream;          /* hipStream_t to issue work on, or NULL (default) */
 } stmg_params;
 
 /* Fill p with the defaults (3D, n=4, r=1, k=1, N=2, tau=0.05, nu=1,
  * r_min=k_min=1, no temporal h-coarsening, placement 0, one pre/post sweep,
- * omega=0.8, FP64, factored Vanka, device 0, default stream). */
+ * omega=0.8, FP64, automatic Vanka form, device 0, default stream). */
 stmg_status stmg_default_params(stmg_params* p);
 
 /* Build the level list of the hp hierarchy without touching a GPU
@@ -217,6 +235,46 @@ typedef struct {
 #define STMG_RESTART 64
 stmg_status stmg_solve(stmg_ctx* ctx, const double* b, double* x, double rtol, int max_it,
                        stmg_solve_info* info);
+
+/* ------------------------------------------------------------------------
+ * Time marching over slabs (Eq. (AlgSysTMS) of Sec. 3.2, with a slab of N
+ * subintervals in place of one) with inhomogeneous Dirichlet data.  The
+ * temporal dofs of a subinterval sit at the right Radau points t_a of DG(k)
+ * (stmg_time_nodes), so the last one is the end value that the next slab's
+ * jump term C^1 V_0 takes.  Dirichlet data are lifted: the library solves
+ * S x0 = b with b = f - S_full gD - C^1 v0 on free rows and 0 on Dirichlet
+ * rows (S_full keeps the Dirichlet columns; gD is g on Dirichlet velocity
+ * entries, 0 elsewhere) and returns x = x0 + gD.
+ * ------------------------------------------------------------------------ */
+
+/* The k+1 reference Radau points t_a in (-1, 1] of the finest level's DG(k)
+ * basis (t_hat: host array of k+1 values); temporal dof a of subinterval n
+ * sits at t0 + tau (n + (t_a + 1) / 2). */
+stmg_status stmg_time_nodes(const stmg_ctx* ctx, double* t_hat);
+
+/* b = f - S_full gD - C^1 v0 on free velocity rows and pressure rows, 0 on
+ * Dirichlet rows (device FP64 slab vectors; f may be NULL for zero forcing,
+ * g NULL for homogeneous data; v0 is a device array of d x nodes velocity
+ * values (one slice of V, component-major), NULL for v0 = 0). */
+stmg_status stmg_slab_rhs(stmg_ctx* ctx, const double* f, const double* v0, const double* g, double* b);
+
+/* v_end = the velocity of the last temporal dof of the last subinterval of
+ * the slab vector x (d x nodes values, device). */
+stmg_status stmg_slab_end_value(stmg_ctx* ctx, const double* x, double* v_end);
+
+/* One slab of the time-marching scheme: b from stmg_slab_rhs, FGMRES as in
+ * stmg_solve (tolerance relative to ||b||), then x = x0 + gD.  Returns what
+ * stmg_solve returns. */
+stmg_status stmg_solve_slab(stmg_ctx* ctx, const double* f, const double* v0, const double* g, double* x,
+                            double rtol, int max_it, stmg_solve_info* info);
+
+/* n_slabs slabs in a row: slab s solves with forcing f + s n_dofs (or 0),
+ * Dirichlet data g + s n_dofs (or 0) and v0 = the end value of slab s - 1
+ * (the given v0, or 0, for s = 0), into x + s n_dofs.  iterations (host,
+ * n_slabs values, may be NULL) receives the FGMRES iterations per slab.
+ * Stops at the first slab that fails (STMG_ENOCONV names it). */
+stmg_status stmg_march(stmg_ctx* ctx, int n_slabs, const double* f, const double* g, const double* v0, double* x,
+                       double rtol, int max_it, int* iterations);
 
 /* x <- x with the L2 mean of the pressure removed in every slice (device
  * vector, finest level). */

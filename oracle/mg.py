@@ -21,7 +21,7 @@ from .vanka import Vanka
 class Multigrid:
     def __init__(self, d, n, r, k, N, tau, nu=1.0, amp=0.0, n_coarse=1, r_min=1,
                  k_min=1, time_h=False, omega=0.8, nu_pre=1, nu_post=1, literal=None,
-                 placement="paper"):
+                 placement="paper", smoother="exact"):
         self.spec = build_levels(n, r, k, N, n_coarse, r_min, k_min, time_h, placement)
         spatial = {}
         self.levels = []
@@ -31,7 +31,7 @@ class Multigrid:
                 spatial[key] = SpatialLevel(d, s["n"], s["r"], amp, nu)
             self.levels.append(SpaceTimeLevel(spatial[key], s["k"], s["N"], tau * N / s["N"]))
         self.P = [prolongation(self.levels[i], self.levels[i + 1]) for i in range(len(self.levels) - 1)]
-        self.smoothers = [Vanka(L, omega, literal) for L in self.levels[:-1]]
+        self.smoothers = [Vanka(L, omega, literal, smoother) for L in self.levels[:-1]]
         self.coarse = CoarseSolver(self.levels[-1])
         self.nu_pre, self.nu_post = nu_pre, nu_post
 

@@ -72,6 +72,32 @@ def local_matrices_factored(L: SpaceTimeLevel, cells=None):
     return np.array(out)
 
 
+def local_matrices_diagonal(L: SpaceTimeLevel, cells=None):
+    """The cheaper patch matrices of the diagonal Vanka (reading G22): A_T of
+    `local_matrices_factored` with its spatial velocity blocks replaced by
+    their diagonals, K (x) diag(M_T) + M^tau (x) diag(A_T), while the coupling
+    of the k+1 temporal dofs and the divergence blocks stay exact (same
+    Dirichlet padding)."""
+    s = L.sp
+    cn = s.vdofs.cell_nodes
+    nc, d, C, nt = s.mesh.n_cells, s.d, s.C, L.nt
+    out = []
+    for T in (range(nc) if cells is None else cells):
+        iv = np.concatenate([c * s.n_nodes + cn[T] for c in range(d)])
+        ip = T * C + np.arange(C)
+        fv = ~s.vel_boundary[iv]
+        Mdiag = np.diag(s.Mh[iv][:, iv].diagonal() * fv)
+        Adiag = np.diag(s.Ah[iv][:, iv].diagonal() * fv)
+        Bloc = s.B[ip][:, iv].toarray() * fv[None, :].astype(float)
+        Avv = np.kron(L.K, Mdiag) + np.kron(L.Mtau, Adiag)
+        Avv += np.kron(np.eye(nt), np.diag((~fv).astype(float)))
+        Avp = -np.kron(L.Mtau, Bloc.T)
+        Apv = -np.kron(L.Mtau, Bloc)
+        App = np.zeros((nt * C, nt * C))
+        out.append(np.block([[Avv, Avp], [Apv, App]]))
+    return np.array(out)
+
+
 def bordered_inverse(L: SpaceTimeLevel, A):
     """Inverse of the whole-domain patch matrices A (one cell) in the mean-zero
     pressure space: the top-left block of [[A, Z], [Z^T, 0]]^{-1}, Z holding
@@ -90,12 +116,18 @@ def bordered_inverse(L: SpaceTimeLevel, A):
 
 
 class Vanka:
-    def __init__(self, L: SpaceTimeLevel, omega, literal=None):
+    """kind "exact": the patch matrices of Eq. (vanka0); "diagonal": the
+    cheaper ones of `local_matrices_diagonal`."""
+
+    def __init__(self, L: SpaceTimeLevel, omega, literal=None, kind="exact"):
         self.L = L
         self.omega = float(omega)
         if literal is None:
             literal = L.ndofs <= 200_000
-        A = local_matrices_literal(L) if literal else local_matrices_factored(L)
+        if kind == "diagonal":
+            A = local_matrices_diagonal(L)
+        else:
+            A = local_matrices_literal(L) if literal else local_matrices_factored(L)
         self.inv = bordered_inverse(L, A) if L.sp.mesh.n_cells == 1 else np.linalg.inv(A)
         self.idx = [cell_dofs(L, n) for n in range(L.N)]
         # valence D: number of spatial cells sharing the dof (pressure: 1)

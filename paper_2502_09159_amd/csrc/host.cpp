@@ -668,6 +668,238 @@ void vanka_dense(const LevelHost& L, const VankaFactors& V, std::vector<double>&
   }
 }
 
+// ------------------------------------------------ temporally decoupled Vanka
+using cplx = std::complex<double>;
+
+// In-place inverse of a row-major complex n x n matrix (Gauss-Jordan with
+// partial pivoting); false if a pivot vanishes.
+static bool cinvert(int n, cplx* A) {
+  std::vector<int> perm(n);
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  for (int j = 0; j < n; ++j) {
+    int p = j;
+    double best = std::abs(A[(size_t)j * n + j]);
+    for (int i = j + 1; i < n; ++i) {
+      double v = std::abs(A[(size_t)i * n + j]);
+      if (v > best) { best = v; p = i; }
+    }
+    if (!(best > 0.0)) return false;
+    if (p != j) {
+      for (int c = 0; c < n; ++c) std::swap(A[(size_t)j * n + c], A[(size_t)p * n + c]);
+      std::swap(perm[j], perm[p]);
+    }
+    const cplx inv = 1.0 / A[(size_t)j * n + j];
+    A[(size_t)j * n + j] = 1.0;
+    for (int c = 0; c < n; ++c) A[(size_t)j * n + c] *= inv;
+    for (int i = 0; i < n; ++i) {
+      if (i == j) continue;
+      const cplx f = A[(size_t)i * n + j];
+      if (f == 0.0) continue;
+      A[(size_t)i * n + j] = 0.0;
+      for (int c = 0; c < n; ++c) A[(size_t)i * n + c] -= f * A[(size_t)j * n + c];
+    }
+  }
+  // the row swaps of the elimination become column swaps of the inverse
+  std::vector<cplx> tmp((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < n; ++c) tmp[(size_t)i * n + perm[c]] = A[(size_t)i * n + c];
+  std::copy(tmp.begin(), tmp.end(), A);
+  return true;
+}
+
+TemporalEigen temporal_eigen(const TimeData& td, double tau) {
+  const int nt = td.k + 1;
+  TemporalEigen E;
+  E.nt = nt;
+  // Kt = diag(c)^{-1} K, c_a = (tau/2) w_a
+  std::vector<double> c(nt), Kt((size_t)nt * nt);
+  for (int a = 0; a < nt; ++a) c[a] = 0.5 * tau * td.w[a];
+  for (int a = 0; a < nt; ++a)
+    for (int b = 0; b < nt; ++b) Kt[(size_t)a * nt + b] = td.K[(size_t)a * nt + b] / c[a];
+  // characteristic polynomial det(z I - Kt) = sum_k p[k] z^k (Faddeev-LeVerrier)
+  std::vector<double> p(nt + 1, 0.0), Mk((size_t)nt * nt, 0.0), AM((size_t)nt * nt);
+  p[nt] = 1.0;
+  for (int k = 1; k <= nt; ++k) {
+    for (int i = 0; i < nt; ++i)  // Mk = Kt M_{k-1} + p[nt-k+1] I
+      for (int j = 0; j < nt; ++j) {
+        double s = 0.0;
+        for (int l = 0; l < nt; ++l) s += Kt[(size_t)i * nt + l] * Mk[(size_t)l * nt + j];
+        AM[(size_t)i * nt + j] = s + (i == j ? p[nt - k + 1] : 0.0);
+      }
+    Mk = AM;
+    double tr = 0.0;
+    for (int i = 0; i < nt; ++i)
+      for (int l = 0; l < nt; ++l) tr += Kt[(size_t)i * nt + l] * Mk[(size_t)l * nt + i];
+    p[nt - k] = -tr / k;
+  }
+  auto poly = [&](cplx z) {
+    cplx v = p[nt];
+    for (int k = nt - 1; k >= 0; --k) v = v * z + p[k];
+    return v;
+  };
+  // roots: Durand-Kerner iteration, then Newton polishing
+  std::vector<cplx> z(nt);
+  double scale = 0.0;
+  for (int k = 0; k < nt; ++k) scale = std::max(scale, std::pow(std::abs(p[k]), 1.0 / (nt - k)));
+  for (int i = 0; i < nt; ++i) z[i] = scale * std::pow(cplx(0.4, 0.9), i);
+  for (int it = 0; it < 500; ++it)
+    for (int i = 0; i < nt; ++i) {
+      cplx den = 1.0;
+      for (int j = 0; j < nt; ++j)
+        if (j != i) den *= z[i] - z[j];
+      z[i] -= poly(z[i]) / den;
+    }
+  for (int i = 0; i < nt; ++i)
+    for (int it = 0; it < 3; ++it) {
+      cplx d = 0.0;  // poly'(z)
+      for (int k = nt; k >= 1; --k) d = d * z[i] + double(k) * p[k];
+      if (std::abs(d) > 0.0) z[i] -= poly(z[i]) / d;
+    }
+  // real eigenvalues first, then one representative (Im > 0) per pair
+  std::vector<cplx> reals, reps;
+  for (cplx v : z) {
+    if (std::abs(v.imag()) <= 1e-10 * std::abs(v)) reals.push_back(cplx(v.real(), 0.0));
+    else if (v.imag() > 0) reps.push_back(v);
+  }
+  if ((int)(reals.size() + 2 * reps.size()) != nt) throw Error(-5, "temporal eigenvalues are not separated");
+  E.nreal = (int)reals.size();
+  E.J = E.nreal + (int)reps.size();
+  E.lam = reals;
+  E.lam.insert(E.lam.end(), reps.begin(), reps.end());
+  // eigenvectors by inverse iteration; W's columns: reals, then rep, conj(rep) per pair
+  auto eigvec = [&](cplx lam) {
+    const cplx sh = lam + cplx(1e-9 * (1.0 + std::abs(lam)), 0.0);
+    std::vector<cplx> A((size_t)nt * nt);
+    for (int i = 0; i < nt; ++i)
+      for (int j = 0; j < nt; ++j) A[(size_t)i * nt + j] = Kt[(size_t)i * nt + j] - (i == j ? sh : 0.0);
+    if (!cinvert(nt, A.data())) throw Error(-5, "temporal eigenvector iteration failed");
+    std::vector<cplx> v(nt, 1.0), w(nt);
+    for (int it = 0; it < 4; ++it) {
+      double nrm = 0.0;
+      for (int i = 0; i < nt; ++i) {
+        cplx s = 0.0;
+        for (int j = 0; j < nt; ++j) s += A[(size_t)i * nt + j] * v[j];
+        w[i] = s;
+        nrm = std::max(nrm, std::abs(s));
+      }
+      int im = 0;
+      for (int i = 0; i < nt; ++i)
+        if (std::abs(w[i]) > std::abs(w[im])) im = i;
+      const cplx ph = w[im];
+      for (int i = 0; i < nt; ++i) v[i] = w[i] / ph;  // largest component 1
+      (void)nrm;
+    }
+    return v;
+  };
+  std::vector<cplx> W((size_t)nt * nt);  // row-major W[a][col]
+  std::vector<int> col_of_block(E.J);
+  int col = 0;
+  for (int j = 0; j < E.J; ++j) {
+    std::vector<cplx> v = eigvec(E.lam[j]);
+    col_of_block[j] = col;
+    if (j < E.nreal) {
+      for (int a = 0; a < nt; ++a) W[(size_t)a * nt + col] = cplx(v[a].real(), 0.0);
+      ++col;
+    } else {
+      for (int a = 0; a < nt; ++a) {
+        W[(size_t)a * nt + col] = v[a];
+        W[(size_t)a * nt + col + 1] = std::conj(v[a]);
+      }
+      col += 2;
+    }
+  }
+  std::vector<cplx> Wi = W;
+  if (!cinvert(nt, Wi.data())) throw Error(-5, "temporal eigenvectors are not independent");
+  E.T.assign((size_t)E.J * nt, 0.0);
+  E.Wt.assign((size_t)nt * E.J, 0.0);
+  for (int j = 0; j < E.J; ++j) {
+    const int cj = col_of_block[j];
+    const bool real = j < E.nreal;
+    for (int a = 0; a < nt; ++a) {
+      cplx t = Wi[(size_t)cj * nt + a] / c[a];
+      cplx w = W[(size_t)a * nt + cj] * (real ? 1.0 : 2.0);
+      if (real) { t = cplx(t.real(), 0.0); w = cplx(w.real(), 0.0); }
+      E.T[(size_t)j * nt + a] = t;
+      E.Wt[(size_t)a * E.J + j] = w;
+    }
+  }
+  return E;
+}
+
+void vanka_decoupled(const LevelHost& L, VankaDecoupled& V, int nthreads, bool diagonal) {
+  const int d = L.d, nl = L.nloc, C = L.C;
+  V.te = temporal_eigen(L.td, L.tau);
+  V.diagonal = diagonal;
+  const int J = V.te.J;
+  if (diagonal) V.Dinv.assign((size_t)L.ncells * J * nl, 0.0);
+  else V.Ainv.assign((size_t)L.ncells * J * nl * nl, 0.0);
+  V.F.assign((size_t)L.ncells * J * d * nl * C, 0.0);
+  V.Hinv.assign((size_t)L.ncells * J * C * C, 0.0);
+  V.Bm.assign((size_t)L.ncells * C * d * nl, 0.0);
+  int fail = 0;
+#pragma omp parallel num_threads(nthreads) reduction(+ : fail)
+  {
+    std::vector<double> Mt((size_t)nl * nl), At((size_t)nl * nl);
+    std::vector<cplx> H((size_t)C * C);
+    std::vector<char> fr(nl);
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t c = 0; c < L.ncells; ++c) {
+      patch_matrices(L, c, Mt.data(), At.data());
+      for (int i = 0; i < nl; ++i) fr[i] = !node_dirichlet(L, c, i);
+      double* Bm = &V.Bm[(size_t)c * C * d * nl];
+      const double* Be = &L.Be[(size_t)c * C * d * nl];
+      for (int l = 0; l < C; ++l)
+        for (int a = 0; a < d; ++a)
+          for (int i = 0; i < nl; ++i)
+            Bm[((size_t)l * d + a) * nl + i] = fr[i] ? Be[((size_t)l * d + a) * nl + i] : 0.0;
+      for (int j = 0; j < J; ++j) {
+        const cplx lam = V.te.lam[j];
+        cplx* F = &V.F[((size_t)c * J + j) * d * nl * C];
+        if (diagonal) {
+          // lambda_j diag(M) + diag(A) on free nodes, 1 on Dirichlet nodes
+          cplx* Dv = &V.Dinv[((size_t)c * J + j) * nl];
+          for (int i = 0; i < nl; ++i) {
+            const cplx dd = fr[i] ? lam * Mt[(size_t)i * nl + i] + At[(size_t)i * nl + i] : cplx(1.0, 0.0);
+            if (!(std::abs(dd) > 0.0)) { ++fail; break; }
+            Dv[i] = 1.0 / dd;
+          }
+          for (int comp = 0; comp < d; ++comp)
+            for (int i = 0; i < nl; ++i)
+              for (int l = 0; l < C; ++l)
+                F[((size_t)comp * nl + i) * C + l] = -Dv[i] * Bm[((size_t)l * d + comp) * nl + i];
+        } else {
+          cplx* Ai = &V.Ainv[((size_t)c * J + j) * nl * nl];
+          for (int i = 0; i < nl; ++i)
+            for (int k = 0; k < nl; ++k)
+              Ai[(size_t)i * nl + k] = (fr[i] && fr[k]) ? lam * Mt[(size_t)i * nl + k] + At[(size_t)i * nl + k]
+                                                        : cplx(i == k ? 1.0 : 0.0, 0.0);
+          if (!cinvert(nl, Ai)) { ++fail; continue; }
+          for (int comp = 0; comp < d; ++comp)
+            for (int i = 0; i < nl; ++i)
+              for (int l = 0; l < C; ++l) {
+                const double* bl = &Bm[((size_t)l * d + comp) * nl];
+                cplx s = 0.0;
+                for (int k = 0; k < nl; ++k) s += Ai[(size_t)i * nl + k] * bl[k];
+                F[((size_t)comp * nl + i) * C + l] = -s;
+              }
+        }
+        for (int l = 0; l < C; ++l)
+          for (int l2 = 0; l2 < C; ++l2) {
+            cplx s = 0.0;
+            for (int comp = 0; comp < d; ++comp) {
+              const double* bl = &Bm[((size_t)l * d + comp) * nl];
+              for (int i = 0; i < nl; ++i) s += bl[i] * F[((size_t)comp * nl + i) * C + l2];
+            }
+            H[(size_t)l * C + l2] = -s;
+          }
+        if (!cinvert(C, H.data())) { ++fail; continue; }
+        std::copy(H.begin(), H.end(), &V.Hinv[((size_t)c * J + j) * C * C]);
+      }
+    }
+  }
+  if (fail) throw Error(-5, "a decoupled cell-patch matrix is singular");
+}
+
 // ------------------------------------------------------------ coarse level
 void coarse_inverse(const LevelHost& L, std::vector<double>& Dinv, std::vector<double>& G) {
   const int d = L.d, nl = L.nloc, C = L.C, nt = L.nt;

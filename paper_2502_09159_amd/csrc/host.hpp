@@ -3,6 +3,7 @@
 // tables and the bordered coarse inverse.  Pure C++ (no HIP); the device side
 // only consumes the arrays built here.
 #pragma once
+#include <complex>
 #include <cstdint>
 #include <functional>
 #include <stdexcept>
@@ -111,6 +112,40 @@ struct VankaFactors {
 void vanka_factors(const LevelHost& L, VankaFactors& V, int nthreads);
 // Dense local inverse (ncells x b x b, col-major) from the factors.
 void vanka_dense(const LevelHost& L, const VankaFactors& V, std::vector<double>& dense, int nthreads);
+
+// Temporal decoupling of the cell-patch matrix (its tensor-product structure
+// in time, the direction the conclusion of the paper points to): the
+// velocity block is A_s = K (x) M_T + diag(c) (x) A_T = (diag(c) (x) I)
+// (Kt (x) M_T + I (x) A_T) with Kt = diag(c)^{-1} K.  With Kt = W Lambda W^{-1},
+// the substitution u = (W (x) I) u~, p = (W (x) I) p~ turns the patch system
+// into one spatial Stokes system per eigenvalue lambda_j:
+//   [[lambda_j M_T + A_T, -B^T], [-B, 0]] [u~_j; p~_j] = (W^{-1} diag(c)^{-1} (x) I) [r_v; r_p]_j.
+// A real Kt has real eigenvalues and complex-conjugate pairs; a pair's
+// systems are conjugate, so one representative (positive imaginary part)
+// is solved and u_a = sum_real W_aj u~_j + sum_pairs 2 Re(W_aj u~_j).
+struct TemporalEigen {
+  int nt = 0, J = 0, nreal = 0;           // J blocks: nreal real eigenvalues first, then the pairs
+  std::vector<std::complex<double>> lam;  // J eigenvalues of Kt
+  std::vector<std::complex<double>> T;    // J x nt: the blocks' rows of W^{-1} diag(c)^{-1}
+  std::vector<std::complex<double>> Wt;   // nt x J: W[a][j], doubled for a pair's representative
+};
+TemporalEigen temporal_eigen(const TimeData& td, double tau);
+
+// Decoupled smoother factors, per cell and block j (FP64, complex):
+// Ainv: (lambda_j M + A)^{-1}, nloc x nloc row-major, M and A the patch
+//       matrices on free nodes and the identity on Dirichlet nodes;
+// F   : F[comp][i][l] = -(Ainv B_comp^T)[i][l] (Dirichlet columns of B zeroed);
+// Hinv: (sum_comp B_comp Ainv B_comp^T)^{-1}, C x C row-major.
+// Bm as in VankaFactors.
+// diagonal = true: the diagonal Vanka's blocks, lambda_j diag(M) + diag(A),
+// stored as Dinv (nloc complex values per block) instead of Ainv.
+struct VankaDecoupled {
+  TemporalEigen te;
+  bool diagonal = false;
+  std::vector<std::complex<double>> Ainv, Dinv, F, Hinv;
+  std::vector<double> Bm;
+};
+void vanka_decoupled(const LevelHost& L, VankaDecoupled& V, int nthreads, bool diagonal = false);
 
 // Coarsest level: the slab matrix is block lower-bidiagonal in time with one
 // diagonal block D per subinterval, so the exact solve is a forward

@@ -198,10 +198,15 @@ __device__ __forceinline__ void pencil(const T (&v)[ZP], T (&o)[ZP], int mat, co
 
 }  // namespace
 
-template <typename T, int D, int Q, int NT>
+// FULL: every column of the operator, Dirichlet ones included (x is read at
+// every node), and for the first subinterval the jump term takes the end
+// value v0 of the previous slab (d x nodes, or none): y = b - S_full x - C^1 v0
+// on free rows, the lifting of inhomogeneous Dirichlet data (Eq. (AlgSysTMS)).
+template <typename T, int D, int Q, int NT, bool FULL = false>
 __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict__ geo, const T* __restrict__ tab,
                                                const T* __restrict__ x, const T* __restrict__ b,
-                                               T* __restrict__ y, T* __restrict__ E, int mode, int nper) {
+                                               T* __restrict__ y, T* __restrict__ E, int mode, int nper,
+                                               const T* __restrict__ v0 = nullptr) {
   constexpr int ZP = D == 3 ? Q : 1;
   constexpr int NL = D == 3 ? Q * Q * Q : Q * Q;
   constexpr int NG = 1 + D * D + D * (D + 1) / 2;
@@ -279,20 +284,23 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
   T* Ec = E + (cc0 * Q + qx) + (int64_t)W * (cc1 * Q + qy) + (D == 3 ? (int64_t)W * W * cc2 * Q : 0);
   const int po = lane16;  // this lane's column of the psi table
 
-  // nodal values of (n, temporal dof bb, comp) interpolated to the Gauss points
+  // nodal values of (n, temporal dof bb, comp) interpolated to the Gauss
+  // points (n = -1: the previous slab's end value v0, FULL only)
   auto interp = [&](int n, int bb, int comp, T (&uq)[ZP]) {
     T v[ZP], w[ZP];
-    const T* xs = x + (int64_t)n * L.slab + (int64_t)bb * L.Mv + (int64_t)comp * L.nodes;
+    const T* xs = (FULL && n < 0) ? v0 + (int64_t)comp * L.nodes
+                                  : x + (int64_t)n * L.slab + (int64_t)bb * L.Mv + (int64_t)comp * L.nodes;
     // FP32: read unconditionally (node 0 stands in for lanes without a free
     // node), so that no load waits behind a per-lane branch (FP64 ran 6%
     // slower so, and keeps the predicated loads)
 #pragma unroll
     for (int z = 0; z < ZP; ++z) {
+      const bool rd = FULL ? lvalid : fre[z];
       if constexpr (sizeof(T) == 4) {
-        const T t = xs[fre[z] ? gnd[z] : 0];
-        v[z] = fre[z] ? t : T(0);
+        const T t = xs[rd ? gnd[z] : 0];
+        v[z] = rd ? t : T(0);
       } else {
-        v[z] = fre[z] ? xs[gnd[z]] : T(0);
+        v[z] = rd ? xs[gnd[z]] : T(0);
       }
     }
     pencil<0, Q, ZP>(v, w, 0, sCX, qx * 4, tS);
@@ -318,6 +326,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
     }
     T up[ZP];
     if (n0 > 0 && n0 < n1) interp(n0 - 1, NT - 1, comp, up);
+    else if (FULL && n0 == 0 && v0 != nullptr) interp(-1, NT - 1, comp, up);
     else
 #pragma unroll
       for (int z = 0; z < ZP; ++z) up[z] = 0;
@@ -489,7 +498,7 @@ __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __res
       for (int j = 0; j < q + 1; ++j) {
         if (j == q && !last) break;
         const int64_t id = row0 + g0 + j;
-        if (KIND == 0) out[id] = mode ? b[id] - xin[id] : xin[id];
+        if (KIND == 0) out[id] = mode == 2 ? T(0) : (mode ? b[id] - xin[id] : xin[id]);
         else out[id] = T(0);
       }
     }
@@ -509,7 +518,7 @@ __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __res
 #pragma unroll
   for (int j = 0; j < q + 1; ++j) {
     const int64_t id = row0 + g0 + j;
-    if (KIND == 0 && mode) bv[j] = b[id];
+    if (KIND == 0 && mode) bv[j] = b[id];  // (modes 1 and 2)
     if (KIND == 1 && !mode) xv[j] = out[id];
   }
   // Dirichlet nodes of the row (x = 0 and x = 1): the operator copies x there
@@ -592,7 +601,7 @@ __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __res
     const T sj = j < q ? (j == 0 && c > 0 ? own[0] + below : own[j < q ? j : 0]) : T(0);
     if (KIND == 0) {
       const T v = dir ? (g == 0 ? xd0 : xd1) : sj;
-      out[id] = mode ? bv[j] - v : v;
+      out[id] = mode == 2 ? (dir ? T(0) : bv[j] - v) : (mode ? bv[j] - v : v);
     } else if (!dir) {
       const T val = (j == 0 && c > 0) ? vyz * T(2) : vyz;
       out[id] = mode ? omega / val * sj : xv[j] + omega / val * sj;
@@ -621,7 +630,9 @@ static hipError_t node_gather(const LevelArgs& L, const T* E, const T* xin, cons
 #define STMG_NG(DD, QQ)                                                                                  \
   if (L.d == DD && L.Q == QQ) {                                                                           \
     const int lxw = gather_lxw(L);                                                                      \
-    if (mode)                                                                                             \
+    if (KIND == 0 && mode == 2)                                                                           \
+      k_node_gather<T, DD, QQ, 0, 2><<<gather_grid<DD>(L, lxw), 256, 0, s>>>(L, E, xin, b, out, omega, lxw); \
+    else if (mode)                                                                                        \
       k_node_gather<T, DD, QQ, KIND, 1><<<gather_grid<DD>(L, lxw), 256, 0, s>>>(L, E, xin, b, out, omega, lxw); \
     else                                                                                                  \
       k_node_gather<T, DD, QQ, KIND, 0><<<gather_grid<DD>(L, lxw), 256, 0, s>>>(L, E, xin, b, out, omega, lxw); \
@@ -661,6 +672,57 @@ hipError_t launch_apply(const LevelArgs& L, const T* geo, const T* tab, const T*
   STMG_AP(3, 4, 1) STMG_AP(3, 4, 2) STMG_AP(3, 4, 3) STMG_AP(3, 4, 4)
 #undef STMG_AP
   return hipErrorInvalidValue;
+}
+
+// b_out = f - S_full g - C^1 v0 on free rows and 0 on Dirichlet rows (FP64):
+// the right-hand side of the homogeneous slab system for forcing f, Dirichlet
+// values g (its entries on free rows are ignored) and the previous slab's end
+// value v0 (d x nodes, or null for v0 = 0).
+template <int D, int Q, int NT>
+static hipError_t lift_impl(const LevelArgs& L, const double* geo, const double* tab, const double* f,
+                            const double* g, const double* v0, double* out, double* E, hipStream_t s) {
+  constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
+  if (L.C != C || L.nt != NT || L.Q != Q || L.nodes >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  const int64_t nbx = (L.Mp / L.C + 15) / 16;
+  // one wave walks every subinterval of its cells: the jump term of the
+  // first one reads v0, the others carry it in registers
+  k_apply<double, D, Q, NT, true><<<dim3((unsigned)nbx, 1), 256, 0, s>>>(L, geo, tab, g, f, out, E, 1, L.N, v0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return node_gather<double, 0>(L, E, g, f, out, 2, 0.0, s);
+}
+
+hipError_t launch_slab_rhs(const LevelArgs& L, const double* geo, const double* tab, const double* f,
+                           const double* g, const double* v0, double* out, double* E, hipStream_t s) {
+#define STMG_LF(DD, QQ, NN) \
+  if (L.d == DD && L.Q == QQ && L.nt == NN) return lift_impl<DD, QQ, NN>(L, geo, tab, f, g, v0, out, E, s);
+  STMG_LF(2, 3, 1) STMG_LF(2, 3, 2) STMG_LF(2, 3, 3) STMG_LF(2, 3, 4)
+  STMG_LF(2, 4, 1) STMG_LF(2, 4, 2) STMG_LF(2, 4, 3) STMG_LF(2, 4, 4)
+  STMG_LF(3, 3, 1) STMG_LF(3, 3, 2) STMG_LF(3, 3, 3) STMG_LF(3, 3, 4)
+  STMG_LF(3, 4, 1) STMG_LF(3, 4, 2) STMG_LF(3, 4, 3) STMG_LF(3, 4, 4)
+#undef STMG_LF
+  return hipErrorInvalidValue;
+}
+
+// x = g on every Dirichlet velocity entry of the slab vector (free entries
+// and pressure untouched)
+__global__ void k_set_dirichlet(LevelArgs L, const double* __restrict__ g, double* __restrict__ x) {
+  const int64_t nv = (int64_t)L.N * L.nt * L.d * L.nodes;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nv; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t node = t % L.nodes, f = t / L.nodes;  // f = (n nt + a) d + comp
+    const int64_t comp = f % L.d, na = f / L.d;
+    const int gx = (int)(node % L.nn), gy = (int)((node / L.nn) % L.nn), gz = L.d == 3 ? (int)(node / ((int64_t)L.nn * L.nn)) : 1;
+    const bool bnd = gx == 0 || gx == L.nn - 1 || gy == 0 || gy == L.nn - 1 || (L.d == 3 && (gz == 0 || gz == L.nn - 1));
+    if (bnd) {
+      const int64_t id = (na / L.nt) * L.slab + (na % L.nt) * L.Mv + comp * L.nodes + node;
+      x[id] = g[id];
+    }
+  }
+}
+
+hipError_t launch_set_dirichlet(const LevelArgs& L, const double* g, double* x, hipStream_t s) {
+  k_set_dirichlet<<<2048, 256, 0, s>>>(L, g, x);
+  return hipGetLastError();
 }
 
 // =====================================================================
@@ -983,6 +1045,471 @@ hipError_t launch_vanka_factored(const LevelArgs& L, const T* Asw, const T* Bm, 
   STMG_VF(3, 3, 1) STMG_VF(3, 3, 2) STMG_VF(3, 3, 3) STMG_VF(3, 3, 4)
   STMG_VF(3, 4, 1) STMG_VF(3, 4, 2) STMG_VF(3, 4, 3) STMG_VF(3, 4, 4)
 #undef STMG_VF
+  return hipErrorInvalidValue;
+}
+
+// =====================================================================
+// Cell Vanka with the temporally decoupled factors (one spatial Stokes block
+// per eigenvalue of diag(c)^{-1} K; host.hpp, TemporalEigen).  One work group
+// per spatial cell, all N subintervals and d components at once:
+//   R~_j = sum_a T_ja R_a                 (velocity and pressure residuals)
+//   Z_j  = Ainv_j R~_j                    (matrix cores; a complex block as
+//                                          the real operands Re / Im Ainv_j)
+//   p~_j = Hinv_j (-B Z_j - R~p_j),  u~_j = Z_j - F_j p~_j
+//   x_p[a] += omega sum_j Re(Wt_aj p~_j),  E[a] = sum_j Re(Wt_aj u~_j)
+// Columns of R~ and Z: comp N + n, padded to DNP = 16 NCT; real parts, then
+// imaginary parts (a real block's are zero and never read).  Block j's Ainv
+// tiles are streamed once from HBM; a complex block needs both Re and Im.
+// =====================================================================
+// DIAG: the diagonal Vanka's blocks lambda_j diag(M) + diag(A): Aw holds
+// their inverses as nloc complex values per block (re, im), Z_j is formed
+// elementwise while the residual is staged, and F_j = -Dinv_j B^T is formed
+// from B (Ft is not read).
+template <typename T, int D, int Q, int NT, int NCT, bool DIAG = false>
+__global__ __launch_bounds__(256) void k_vanka_tdec(LevelArgs L, const T* __restrict__ Aw,
+                                                    const T* __restrict__ Bm, const T* __restrict__ Ft,
+                                                    const T* __restrict__ Ht, const T* __restrict__ tw,
+                                                    const T* __restrict__ r, T* __restrict__ x, T omega,
+                                                    T* __restrict__ E, int xzero) {
+  constexpr int NL = D == 3 ? Q * Q * Q : Q * Q;
+  constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
+  constexpr int MP = (NL + 15) / 16 * 16, NKB = MP / 16;
+  constexpr int J = (NT + 1) / 2, NR = NT % 2;  // blocks; block 0 is real iff NT is odd
+  constexpr int DNP = NCT * 16, NCOL = 2 * DNP, ZS = NCOL + 1;
+  constexpr int RT = J * NKB;                   // row tiles (16 rows of one block)
+  constexpr int CSPL = RT >= 4 ? 1 : 4 / RT;    // waves that share a row tile split its column tiles
+  constexpr int TPW = (RT + 3) / 4;             // row tiles per wave
+  constexpr int R4 = (2 * C + 3) / 4 * 4;       // vanka_tdec_row(C)
+  typedef typename mfma_vec<T>::v4 v4;
+  const int N = L.N, lgN = N == 1 ? 0 : (N == 2 ? 1 : (N == 4 ? 2 : 3)), DN = D * N;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* RZ = reinterpret_cast<T*>(smem_raw);  // R~ in B-operand order, then Z as [j][row][ZS]
+  T* sB = RZ + J * MP * ZS;                // B of this cell, [comp][i][l]
+  T* Rp = sB + C * D * NL;                 // pressure residual as read, [a C + l][n]
+  T* Sr = Rp + NT * C * 8;                 // Schur right-hand side [j C + l][n], real / imaginary
+  T* Si = Sr + J * C * 8;
+  T* Pr = Si + J * C * 8;                  // p~ [j C + l][n], real / imaginary
+  T* Pi = Pr + J * C * 8;
+  T* Sp = Pi + J * C * 8;                  // per wave: partial (B Z_j)^T tiles [wave][j][16][17]
+  const T* tT = tw;                  // T[j][a] (re, im)
+  const T* tW = tw + 2 * J * NT;     // Wt[a][j] (re, im)
+  const int64_t cell = xcd_remap(blockIdx.x, gridDim.x);
+  const int cc[3] = {(int)(cell % L.n), (int)((cell / L.n) % L.n), D == 3 ? (int)(cell / ((int64_t)L.n * L.n)) : 0};
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  auto ridx = [](int j, int part, int ct, int kb, int ln, int slot) {
+    return ((((j * 2 + part) * NCT + ct) * NKB + kb) * 64 + ln) * 4 + slot;
+  };
+
+  // ---- Ainv fragments of this wave's first row tile (issued right after
+  // the residual loads, consumed after the barrier)
+  const T* A = Aw + cell * (int64_t)(DIAG ? 2 * J * NL : NT * MP * MP);
+  T fx[NKB][4], fy[NKB][4];
+  auto load_tile = [&](int t) {
+    if constexpr (DIAG) return;
+    const int j = t / NKB, lt = t % NKB;
+    const T* X = A + (int64_t)(j < NR ? j : 2 * j - NR) * MP * MP + (int64_t)lt * NKB * 256 + lane * 4;
+    const T* Y = j < NR ? X : X + MP * MP;  // (a real block reads its Re tile twice; unused)
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl) {
+        fx[kb][sl] = X[kb * 256 + sl];
+        fy[kb][sl] = Y[kb * 256 + sl];
+      }
+  };
+  const int t_first = CSPL > 1 ? wave % RT : min(wave, RT - 1);
+
+  // ---- residual rows to the temporal eigenbasis, in B-operand order.  Items
+  // (n, comp, x-row), n fastest; each reads the x-row (Q nodes) of every
+  // temporal dof, zeroes Dirichlet entries and writes R~_j of its Q nodes.
+  {
+    constexpr int ROWS = NL / Q;
+    constexpr int IMAX = (ROWS * D * 8 + 255) / 256;  // N <= 8
+    constexpr int PB = (C * D * NL + 255) / 256;
+    constexpr int PR = (NT * C * 8 + 255) / 256;
+    const int nitems = ROWS * DN;
+    const T* Bc = Bm + cell * (int64_t)C * D * NL;
+    T rv[IMAX][NT][Q], bv[PB], pv[PR];
+    bool rok[IMAX];
+    // unconditional loads from clamped (in-bounds) addresses
+#pragma unroll
+    for (int e = 0; e < IMAX; ++e) {
+      const int it = min(tid + 256 * e, nitems - 1);
+      const int n = it & (N - 1), rest = it >> lgN, comp = rest % D, row = rest / D;
+      const int iy = row % Q, iz = row / Q;
+      const int gy = cc[1] * (Q - 1) + iy, gz = D == 3 ? cc[2] * (Q - 1) + iz : 1;
+      rok[e] = tid + 256 * e < nitems && gy > 0 && gy < L.nn - 1 && gz > 0 && (D == 2 || gz < L.nn - 1);
+      const int64_t g = (int64_t)cc[0] * (Q - 1) + (int64_t)L.nn * (gy + (D == 3 ? (int64_t)L.nn * gz : 0));
+#pragma unroll
+      for (int a = 0; a < NT; ++a) __builtin_memcpy(rv[e][a], r + vidx(L, n, a, comp, g), sizeof(T) * Q);
+    }
+#pragma unroll
+    for (int e = 0; e < PB; ++e) bv[e] = Bc[min(tid + 256 * e, C * D * NL - 1)];
+#pragma unroll
+    for (int e = 0; e < PR; ++e) {
+      const int t = min(tid + 256 * e, NT * C * N - 1), q = t >> lgN, n = t & (N - 1);
+      pv[e] = r[pidx(L, n, q / C, cell, q % C)];
+    }
+    load_tile(t_first);
+    // padding entries (rows >= NL or columns >= d N): only the last row tile
+    // and the last column tile hold any; one entry of a tile per thread.
+    // DIAG writes Z directly: its rows NL..MP-1 are zeroed instead.
+    if constexpr (DIAG) {
+      for (int idx = tid; idx < J * (MP - NL) * NCOL; idx += 256) {
+        const int j = idx / ((MP - NL) * NCOL), rest = idx % ((MP - NL) * NCOL);
+        RZ[(j * MP + NL + rest / NCOL) * ZS + rest % NCOL] = T(0);
+      }
+    } else {
+      const int l64 = tid >> 2, sl = tid & 3;
+      for (int tile = 0; tile < J * 2 * NCT * NKB; ++tile) {
+        const int kb = tile % NKB, ct = (tile / NKB) % NCT;
+        if (!((kb == NKB - 1 && NL < MP) || (ct == NCT - 1 && DN < DNP))) continue;  // (uniform)
+        const int K = kb * 16 + 4 * (l64 >> 4) + sl, col = ct * 16 + (l64 & 15);
+        if (K >= NL || col >= DN) RZ[tile * 256 + tid] = T(0);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < IMAX; ++e) {
+      const int it = tid + 256 * e;
+      if (it < nitems) {
+        const int n = it & (N - 1), rest = it >> lgN, comp = rest % D, row = rest / D;
+        const int col = comp * N + n, ct = col / 16, jj = col % 16, K0 = row * Q;
+#pragma unroll
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+          for (int q = 0; q < Q; ++q)
+            if (!rok[e] || (q == 0 && cc[0] == 0) || (q == Q - 1 && cc[0] == L.n - 1)) rv[e][a][q] = T(0);
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          T tr[NT], ti[NT];
+#pragma unroll
+          for (int a = 0; a < NT; ++a) {
+            tr[a] = tT[(j * NT + a) * 2];
+            ti[a] = tT[(j * NT + a) * 2 + 1];
+          }
+          T sr[Q], si[Q];
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            sr[q] = 0;
+            si[q] = 0;
+#pragma unroll
+            for (int a = 0; a < NT; ++a) {
+              sr[q] += tr[a] * rv[e][a][q];
+              si[q] += ti[a] * rv[e][a][q];
+            }
+          }
+          if constexpr (DIAG) {
+            // Z_j = Dinv_j R~_j, written in Z's row-major layout
+            const T* dv = A + (j * NL + K0) * 2;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+              const T dr = dv[2 * q], di = dv[2 * q + 1];
+              T* zz = RZ + (j * MP + K0 + q) * ZS + col;
+              zz[0] = dr * sr[q] - di * si[q];
+              zz[DNP] = dr * si[q] + di * sr[q];
+            }
+          } else if constexpr (Q == 4) {
+            // the row's 4 nodes are the 4 slots of one lane: one wide store
+            const int ln = jj + 16 * (row % 4);
+            __builtin_memcpy(RZ + ridx(j, 0, ct, row / 4, ln, 0), sr, sizeof(sr));
+            if (j >= NR) __builtin_memcpy(RZ + ridx(j, 1, ct, row / 4, ln, 0), si, sizeof(si));
+          } else {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+              const int K = K0 + q, kb = K / 16, rem = K % 16, ln = jj + 16 * (rem / 4);
+              RZ[ridx(j, 0, ct, kb, ln, rem % 4)] = sr[q];
+              if (j >= NR) RZ[ridx(j, 1, ct, kb, ln, rem % 4)] = si[q];
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < PB; ++e) {
+      const int idx = tid + 256 * e;  // global order [l][comp][i]
+      if (idx < C * D * NL) {
+        const int l = idx / (D * NL), ci = idx - l * (D * NL);
+        sB[ci * C + l] = bv[e];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < PR; ++e)
+      if (tid + 256 * e < NT * C * N) Rp[tid + 256 * e] = pv[e];
+  }
+  __syncthreads();
+
+  // ---- Z_j = Ainv_j R~_j on the matrix cores, one 16-row tile at a time:
+  // Re Z = X Re R~ - Y Im R~, Im Z = X Im R~ + Y Re R~ (X, Y: Re, Im Ainv_j)
+  v4 accR[TPW][NCT], accI[TPW][NCT];
+  const int cpart = CSPL > 1 ? wave / RT : 0;
+#pragma unroll
+  for (int it = 0; it < (DIAG ? 0 : TPW); ++it) {
+    const int t = CSPL > 1 ? t_first : wave + 4 * it;
+    if (it > 0) load_tile(min(t, RT - 1));  // unconditional (clamped): exact wait counts
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      accR[it][ct] = v4{0, 0, 0, 0};
+      accI[it][ct] = v4{0, 0, 0, 0};
+    }
+    const bool active = t < RT && (CSPL == 1 || wave < RT * CSPL);
+    if (active) {
+      const int j = t / NKB;
+      if (j >= NR) {
+        T ny[NKB][4];
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+          for (int sl = 0; sl < 4; ++sl) ny[kb][sl] = -fy[kb][sl];
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+          for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) {
+              if (CSPL > 1 && ct % CSPL != cpart) continue;
+              const T bR = RZ[ridx(j, 0, ct, kb, lane, sl)], bI = RZ[ridx(j, 1, ct, kb, lane, sl)];
+              accR[it][ct] = mfma_vec<T>::mma(fx[kb][sl], bR, accR[it][ct]);
+              accI[it][ct] = mfma_vec<T>::mma(fx[kb][sl], bI, accI[it][ct]);
+              accR[it][ct] = mfma_vec<T>::mma(ny[kb][sl], bI, accR[it][ct]);
+              accI[it][ct] = mfma_vec<T>::mma(fy[kb][sl], bR, accI[it][ct]);
+            }
+      } else {
+#pragma unroll
+        for (int kb = 0; kb < NKB; ++kb)
+#pragma unroll
+          for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) {
+              if (CSPL > 1 && ct % CSPL != cpart) continue;
+              accR[it][ct] = mfma_vec<T>::mma(fx[kb][sl], RZ[ridx(j, 0, ct, kb, lane, sl)], accR[it][ct]);
+            }
+      }
+    }
+  }
+  __syncthreads();  // every wave is done reading R~
+#pragma unroll
+  for (int it = 0; it < (DIAG ? 0 : TPW); ++it) {
+    const int t = CSPL > 1 ? t_first : wave + 4 * it;
+    const bool active = t < RT && (CSPL == 1 || wave < RT * CSPL);
+    if (active) {
+      const int j = t / NKB, lt = t % NKB;
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) {
+        if (CSPL > 1 && ct % CSPL != cpart) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          T* zr = RZ + (j * MP + lt * 16 + mfma_vec<T>::row(lane, v)) * ZS + ct * 16 + lane % 16;
+          zr[0] = accR[it][ct][v];
+          zr[DNP] = accI[it][ct][v];  // zero for a real block
+        }
+      }
+    }
+  }
+  // F and Hinv rows of this thread and the old pressure values, issued now
+  // (the Ainv fragments are dead) so that their latency overlaps the Schur
+  // complement
+  constexpr int RPT = (D * NL + 255) / 256;       // velocity rows (comp, i) per thread
+  constexpr int HPT = (J * C * 8 + 255) / 256;    // (j, l', n) items per thread, N <= 8
+  constexpr int XPT = (NT * C * 8 + 255) / 256;   // (a, l, n) items per thread
+  const T* Fc = Ft + cell * (int64_t)J * D * NL * R4;
+  const T* Hc = Ht + cell * (int64_t)J * C * R4;
+  T fv[RPT][J][2 * C], hv[HPT][2 * C], xp[XPT];
+#pragma unroll
+  for (int h = 0; h < HPT; ++h) {
+    const int t = min(tid + 256 * h, J * C * N - 1), pp = t >> lgN;
+    T hrow[R4];
+    __builtin_memcpy(hrow, __builtin_assume_aligned(Hc + pp * R4, 16), sizeof(T) * R4);
+#pragma unroll
+    for (int q = 0; q < 2 * C; ++q) hv[h][q] = hrow[q];
+  }
+#pragma unroll
+  for (int e = 0; e < XPT; ++e) {
+    const int t = min(tid + 256 * e, NT * C * N - 1), q = t >> lgN, n = t & (N - 1);
+    xp[e] = x[pidx(L, n, q / C, cell, q % C)];
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int row2 = min(tid + 256 * k, D * NL - 1);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      if constexpr (DIAG) {  // F_j[comp][i][l] = -Dinv_j[i] B[l][comp][i] (B in LDS since the first barrier)
+        const int i = row2 % NL;
+        const T dr = A[(j * NL + i) * 2], di = A[(j * NL + i) * 2 + 1];
+#pragma unroll
+        for (int l = 0; l < C; ++l) {
+          const T bb = sB[row2 * C + l];
+          fv[k][j][2 * l] = -dr * bb;
+          fv[k][j][2 * l + 1] = -di * bb;
+        }
+      } else {
+        T frow[R4];
+        __builtin_memcpy(frow, __builtin_assume_aligned(Fc + ((int64_t)j * D * NL + row2) * R4, 16), sizeof(T) * R4);
+#pragma unroll
+        for (int q = 0; q < 2 * C; ++q) fv[k][j][q] = frow[q];
+      }
+    }
+  }
+  __syncthreads();
+  const T* Z = RZ;
+
+  // ---- Schur complement right-hand side S_j = -B Z_j - R~p_j.  (B Z_j)^T on
+  // the matrix cores: rows m = 8 part + n (real / imaginary part of Z_j's
+  // column (comp, n)), columns l, k = comp MP + i, the k-blocks split over the
+  // waves; rows i >= NL of Z_j are zero (so are Ainv_j's padding rows), and
+  // rows n >= N and columns l >= C are not used (their operands are clamped)
+  {
+    constexpr int KB = D * MP / 16, KPW = (KB + 3) / 4;
+    const int m = lane % 16, part = m / 8, nz = min(m % 8, N - 1), lc = min(lane % 16, C - 1);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      v4 sacc = v4{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < KPW; ++kk) {
+        const int kb = wave + 4 * kk;
+        if (kb < KB) {
+#pragma unroll
+          for (int sl = 0; sl < 4; ++sl) {
+            const int k = kb * 16 + 4 * (lane / 16) + sl, comp = k / MP, i = k % MP;
+            const T av = Z[(j * MP + i) * ZS + part * DNP + comp * N + nz];
+            const T bvv = sB[(comp * NL + min(i, NL - 1)) * C + lc];
+            sacc = mfma_vec<T>::mma(av, bvv, sacc);
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Sp[((wave * J + j) * 16 + mfma_vec<T>::row(lane, v)) * 17 + lane % 16] = sacc[v];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < J * C * N; t += 256) {
+    const int n = t & (N - 1), q = t >> lgN, j = q / C, l = q % C;
+    T sr = 0, si = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      sr += Sp[((w * J + j) * 16 + n) * 17 + l];
+      si += Sp[((w * J + j) * 16 + 8 + n) * 17 + l];
+    }
+    T pr = 0, pi = 0;
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      const T v = Rp[(a * C + l) * N + n];
+      pr += tT[(j * NT + a) * 2] * v;
+      pi += tT[(j * NT + a) * 2 + 1] * v;
+    }
+    Sr[q * N + n] = -sr - pr;
+    Si[q * N + n] = -si - pi;
+  }
+  __syncthreads();
+  // ---- p~_j = Hinv_j S_j
+#pragma unroll
+  for (int h = 0; h < HPT; ++h) {
+    const int t = tid + 256 * h;
+    if (t < J * C * N) {
+      const int pp = t >> lgN, n = t & (N - 1), j = pp / C;
+      T pr = 0, pi = 0;
+#pragma unroll
+      for (int l = 0; l < C; ++l) {
+        const T hr = hv[h][2 * l], hi = hv[h][2 * l + 1];
+        const T sr = Sr[(j * C + l) * N + n], si = Si[(j * C + l) * N + n];
+        pr += hr * sr - hi * si;
+        pi += hr * si + hi * sr;
+      }
+      Pr[pp * N + n] = pr;
+      Pi[pp * N + n] = pi;
+    }
+  }
+  __syncthreads();
+  // ---- pressure: x_p[a] += omega sum_j Re(Wt_aj p~_j) (cell-owned dofs)
+#pragma unroll
+  for (int e = 0; e < XPT; ++e) {
+    const int t = tid + 256 * e;
+    if (t < NT * C * N) {
+      const int q = t >> lgN, n = t & (N - 1), a = q / C, l = q % C;
+      T v = 0;
+#pragma unroll
+      for (int j = 0; j < J; ++j)
+        v += tW[(a * J + j) * 2] * Pr[(j * C + l) * N + n] - tW[(a * J + j) * 2 + 1] * Pi[(j * C + l) * N + n];
+      x[pidx(L, n, a, cell, l)] = (xzero ? T(0) : xp[e]) + omega * v;
+    }
+  }
+  // ---- velocity: u~_j = Z_j - F_j p~_j, E[a] = sum_j Re(Wt_aj u~_j) (cell-major)
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int row2 = tid + 256 * k;
+    if (row2 >= D * NL) break;
+    const int comp = row2 / NL, i = row2 % NL;
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+      if (n >= N) break;
+      T ur[J], ui[J];
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const T* zz = Z + (j * MP + i) * ZS + comp * N + n;
+        T vr = zz[0], vi = zz[DNP];
+#pragma unroll
+        for (int l = 0; l < C; ++l) {
+          const T fr = fv[k][j][2 * l], fi = fv[k][j][2 * l + 1];
+          const T pr = Pr[(j * C + l) * N + n], pi = Pi[(j * C + l) * N + n];
+          vr -= fr * pr - fi * pi;
+          vi -= fr * pi + fi * pr;
+        }
+        ur[j] = vr;
+        ui[j] = vi;
+      }
+#pragma unroll
+      for (int a = 0; a < NT; ++a) {
+        T v = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j) v += tW[(a * J + j) * 2] * ur[j] - tW[(a * J + j) * 2 + 1] * ui[j];
+        E[e_index(L, (int64_t)(n * NT + a) * D + comp, cell, i)] = v;
+      }
+    }
+  }
+}
+
+template <typename T, int D, int Q, int NT, bool DIAG>
+static hipError_t vanka_tdec_impl(const LevelArgs& L, const T* Aw, const T* Bm, const T* Ft, const T* Ht,
+                                  const T* tw, const T* r, T* x, T omega, T* E, hipStream_t s, bool gather,
+                                  bool xzero) {
+  constexpr int NL = D == 3 ? Q * Q * Q : Q * Q;
+  constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
+  constexpr int MP = (NL + 15) / 16 * 16, J = (NT + 1) / 2;
+  if (L.C != C || L.nloc != NL || L.nt != NT || L.N < 1 || L.N > 8 || (L.N & (L.N - 1))) return hipErrorInvalidValue;
+  const int64_t ncells = L.Mp / L.C;
+  const int DN = D * L.N;
+  auto shm = [&](int dnp) {
+    return sizeof(T) * ((size_t)J * MP * (2 * dnp + 1) + (size_t)C * D * NL + (size_t)NT * C * 8 + 4 * (size_t)J * C * 8 +
+                        (size_t)4 * J * 16 * 17);
+  };
+  auto run = [&](auto kern, size_t bytes) -> hipError_t {
+    if (bytes > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      if (e != hipSuccess) return e;
+    }
+    kern<<<(unsigned)ncells, 256, bytes, s>>>(L, Aw, Bm, Ft, Ht, tw, r, x, omega, E, xzero ? 1 : 0);
+    return hipGetLastError();
+  };
+  hipError_t e;
+  if (DN <= 16) e = run(k_vanka_tdec<T, D, Q, NT, 1, DIAG>, shm(16));
+  else if (DN <= 32) e = run(k_vanka_tdec<T, D, Q, NT, 2, DIAG>, shm(32));
+  else return hipErrorInvalidValue;
+  if (e != hipSuccess || !gather) return e;
+  return vanka_gather<T>(L, E, x, omega, s, xzero);
+}
+
+template <typename T>
+hipError_t launch_vanka_decoupled(const LevelArgs& L, const T* Aw, const T* Bm, const T* Ft, const T* Ht,
+                                  const T* tw, const T* r, T* x, T omega, T* E, hipStream_t s, bool gather,
+                                  bool xzero, bool diagonal) {
+#define STMG_VT(DD, QQ, KK)                                                                                   \
+  if (L.d == DD && L.Q == QQ && L.nt == KK)                                                                   \
+    return diagonal ? vanka_tdec_impl<T, DD, QQ, KK, true>(L, Aw, Bm, Ft, Ht, tw, r, x, omega, E, s, gather, xzero) \
+                    : vanka_tdec_impl<T, DD, QQ, KK, false>(L, Aw, Bm, Ft, Ht, tw, r, x, omega, E, s, gather, xzero);
+  STMG_VT(2, 3, 1) STMG_VT(2, 3, 2) STMG_VT(2, 3, 3) STMG_VT(2, 3, 4)
+  STMG_VT(2, 4, 1) STMG_VT(2, 4, 2) STMG_VT(2, 4, 3) STMG_VT(2, 4, 4)
+  STMG_VT(3, 3, 1) STMG_VT(3, 3, 2) STMG_VT(3, 3, 3) STMG_VT(3, 3, 4)
+  STMG_VT(3, 4, 1) STMG_VT(3, 4, 2) STMG_VT(3, 4, 3) STMG_VT(3, 4, 4)
+#undef STMG_VT
   return hipErrorInvalidValue;
 }
 
@@ -1988,6 +2515,8 @@ hipError_t launch_project_pressure(const LevelArgs& L, const double* mom, double
   template hipError_t launch_vanka_factored<T>(const LevelArgs&, const T*, const T*, const T*, const T*, const T*, \
                                                const T*, T*, T, T*, hipStream_t, bool, bool);                       \
   template hipError_t launch_vanka_dense<T>(const LevelArgs&, const T*, const T*, T*, T, hipStream_t);             \
+  template hipError_t launch_vanka_decoupled<T>(const LevelArgs&, const T*, const T*, const T*, const T*,          \
+                                                const T*, const T*, T*, T, T*, hipStream_t, bool, bool, bool);      \
   template hipError_t launch_prolongate_add<T>(const LevelArgs&, const LevelArgs&, const TransferDev&, const T*,   \
                                                const int*, const int*, const T*, const T*, const T*, T*, T*, T*,    \
                                                T*, hipStream_t);                                                    \

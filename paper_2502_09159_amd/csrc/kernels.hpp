@@ -44,6 +44,17 @@ template <typename T>
 hipError_t launch_apply(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y, int mode,
                         T* E, hipStream_t s, bool gather = true, int nper = 0);
 
+// Slab right-hand side for time marching (Eq. (AlgSysTMS)) with lifted
+// Dirichlet data, FP64: out = f - S_full g - C^1 v0 on free velocity rows and
+// on pressure rows, 0 on Dirichlet rows.  S_full keeps every column of the
+// operator; g supplies the Dirichlet values (its free entries are ignored);
+// v0 (d x nodes, may be null) is the end value of the previous slab.  E is
+// the level's cell scratch.
+hipError_t launch_slab_rhs(const LevelArgs& L, const double* geo, const double* tab, const double* f,
+                           const double* g, const double* v0, double* out, double* E, hipStream_t s);
+// x = g on the Dirichlet velocity entries of a slab vector.
+hipError_t launch_set_dirichlet(const LevelArgs& L, const double* g, double* x, hipStream_t s);
+
 // Vanka correction with factored local inverses: x += omega D^-1 sum R^T A^-1 R r.
 // Asw: A_s^{-1} of every cell in MFMA operand order (see vanka_swizzle_index),
 // padded to mp = 16 ceil(m/16); E: cell-local scratch of ncells * d * m * N
@@ -63,6 +74,30 @@ inline int64_t vanka_swizzle_index(int mp, int row, int k) {
   int t = row / 16, kb = k / 16, lane = row % 16 + 16 * ((k % 16) / 4), sl = k % 4;
   return (((int64_t)t * (mp / 16) + kb) * 64 + lane) * 4 + sl;
 }
+// Vanka correction with the temporally decoupled factors (one spatial Stokes
+// block per eigenvalue of diag(c)^{-1} K: the real ones first, then one
+// representative per complex-conjugate pair; the block count J and the number
+// of real blocks follow from nt: J = (nt + 1) / 2, one real block iff nt is
+// odd).  Per cell:
+//   Aw: per block, Re (Ainv_j) then, for a complex block, Im (Ainv_j), each
+//       mp x mp (mp = 16 ceil(nloc / 16)) in MFMA operand order
+//       (vanka_swizzle_index);
+//   Bm: C x d x nloc (as for the coupled factors);
+//   Ft: [j][comp][i][row] with row = (re, im) of F_j[comp][i][l] for l < C,
+//       padded to vanka_tdec_row(C) values;
+//   Ht: [j][l][row] with row = (re, im) of Hinv_j[l][l'], padded likewise;
+//   tw: per level, T (J x nt complex, (re, im)) then Wt (nt x J complex).
+inline int vanka_tdec_row(int C) { return (2 * C + 3) / 4 * 4; }
+inline int64_t vanka_tdec_aw(int nloc, int nt) {
+  const int64_t mp = (nloc + 15) / 16 * 16;
+  return (int64_t)nt * mp * mp;  // 2 J - nreal = nt blocks of mp^2
+}
+// diagonal: the diagonal Vanka (blocks lambda_j diag(M) + diag(A)): Aw holds
+// nloc complex inverse diagonal entries per block (re, im) and Ft is unused.
+template <typename T>
+hipError_t launch_vanka_decoupled(const LevelArgs& L, const T* Aw, const T* Bm, const T* Ft, const T* Ht,
+                                  const T* tw, const T* r, T* x, T omega, T* E, hipStream_t s,
+                                  bool gather = true, bool xzero = false, bool diagonal = false);
 // x_v += omega / valence * sum_cells E (the velocity half of a patch update).
 template <typename T>
 hipError_t launch_vanka_gather_only(const LevelArgs& L, const T* E, T* x, T omega, hipStream_t s);

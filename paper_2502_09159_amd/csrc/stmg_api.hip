@@ -74,6 +74,7 @@ struct Pool {
 template <typename T>
 struct DevLevel {
   LevelArgs a{};
+  int vform = STMG_VANKA_FACTORED;  // stored form of this level's local inverses
   T* tab = nullptr;
   T* geo = nullptr;  // Gauss-point geometry of the operator kernel
   T *Asw = nullptr, *Bm = nullptr, *F = nullptr, *Hinv = nullptr, *coef = nullptr, *dense = nullptr;
@@ -161,6 +162,8 @@ struct stmg_ctx {
   bool net_ready = false, learned_on = false, learned_disabled = false;
   int learned_reading = 1;  // 1: every level reaching a Q2/P1 x DG(1) level on its mesh; 2: those levels only
   std::vector<void*> lsave;  // per level: copy of x before a correction
+  // time marching: right-hand side and Dirichlet values of the current slab
+  double *slab_b = nullptr, *slab_g = nullptr;
   // execution options (stmg_set_option)
   int opt_apply_nper = 0;      // subintervals per wave of the operator's cell kernel (0: automatic)
   int64_t opt_net_chunk = 0;   // space-time cells per inference chunk (0: the default)
@@ -189,9 +192,23 @@ std::vector<double> pack_tables(const LevelHost& L) {
   return t;
 }
 
+// The stored form of a level's local inverses: the requested one, or for
+// STMG_VANKA_AUTO the one measured faster at that element (the decoupled form
+// halves the bytes of the dominant factor, which pays on levels with 64 and
+// more velocity nodes per cell; below, the per-cell fixed costs dominate and
+// the Schur-factored kernel is faster).
+constexpr int kFormDiagonal = 4;  // the diagonal Vanka (decoupled, diagonal spatial blocks)
+
+int vanka_form(const stmg_params& p, const LevelHost& L) {
+  if (p.local_solver == STMG_LOCAL_DIAGONAL) return kFormDiagonal;
+  if (p.vanka_mode != STMG_VANKA_AUTO) return p.vanka_mode;
+  return L.nloc >= 64 ? STMG_VANKA_DECOUPLED : STMG_VANKA_FACTORED;
+}
+
 template <typename T>
 void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
-                const std::vector<std::vector<double>>& dense, bool with_vanka) {
+                const std::vector<std::vector<double>>& dense, const std::vector<VankaDecoupled>& VD,
+                bool with_vanka) {
   hipStream_t s = c->stream;
   const size_t nlev = c->host.size();
   H.L.resize(nlev);
@@ -199,6 +216,7 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
     const LevelHost& L = c->host[l];
     DevLevel<T>& D = H.L[l];
     D.a = level_args(L);
+    D.vform = vanka_form(c->p, L);
     D.tab = c->pool.upload<T>(pack_tables(L), s);
     {
       std::vector<double> g;
@@ -211,10 +229,84 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
     D.b = c->pool.alloc<T>(L.ndofs);
     D.x = c->pool.alloc<T>(L.ndofs);
     D.r = c->pool.alloc<T>(L.ndofs);
-    if (with_vanka && l + 1 < nlev) {
+    if (with_vanka && l + 1 < nlev && D.vform == kFormDiagonal) {
+      const VankaDecoupled& V = VD[l];
+      const int J = V.te.J, nt = L.nt, nl = L.nloc, C = L.C;
+      const int R4 = vanka_tdec_row(C);
+      if (V.te.nreal != nt % 2 || J != (nt + 1) / 2)
+        throw Error(STMG_EUNSUPPORTED, "unexpected eigenvalue structure of the temporal matrix");
+      std::vector<double> tw;
+      for (const auto& z : V.te.T) { tw.push_back(z.real()); tw.push_back(z.imag()); }
+      for (const auto& z : V.te.Wt) { tw.push_back(z.real()); tw.push_back(z.imag()); }
+      D.coef = c->pool.upload<T>(tw, s);
+      std::vector<T> Dw((size_t)L.ncells * J * nl * 2), Hr((size_t)L.ncells * J * C * R4, T(0));
+      for (size_t i = 0; i < V.Dinv.size(); ++i) {
+        Dw[2 * i] = (T)V.Dinv[i].real();
+        Dw[2 * i + 1] = (T)V.Dinv[i].imag();
+      }
+      for (int64_t cl = 0; cl < L.ncells; ++cl)
+        for (int j = 0; j < J; ++j) {
+          const std::complex<double>* Hi = &V.Hinv[((size_t)cl * J + j) * C * C];
+          for (int l = 0; l < C; ++l)
+            for (int l2 = 0; l2 < C; ++l2) {
+              T* h = &Hr[(((size_t)cl * J + j) * C + l) * R4 + 2 * l2];
+              h[0] = (T)Hi[(size_t)l * C + l2].real();
+              h[1] = (T)Hi[(size_t)l * C + l2].imag();
+            }
+        }
+      D.Asw = c->pool.upload<T>(Dw, s);
+      D.Bm = c->pool.upload<T>(V.Bm, s);
+      D.Hinv = c->pool.upload<T>(Hr, s);
+    } else if (with_vanka && l + 1 < nlev && D.vform == STMG_VANKA_DECOUPLED) {
+      const VankaDecoupled& V = VD[l];
+      const int J = V.te.J, nt = L.nt, nl = L.nloc, C = L.C, d = L.d;
+      const int mp = (nl + 15) & ~15, R4 = vanka_tdec_row(C);
+      if (V.te.nreal != nt % 2 || J != (nt + 1) / 2)
+        throw Error(STMG_EUNSUPPORTED, "unexpected eigenvalue structure of the temporal matrix");
+      // per level: T (J x nt) then Wt (nt x J), complex as (re, im)
+      std::vector<double> tw;
+      for (const auto& z : V.te.T) { tw.push_back(z.real()); tw.push_back(z.imag()); }
+      for (const auto& z : V.te.Wt) { tw.push_back(z.real()); tw.push_back(z.imag()); }
+      D.coef = c->pool.upload<T>(tw, s);
+      const int64_t aw = vanka_tdec_aw(nl, nt);
+      std::vector<T> A((size_t)L.ncells * aw, T(0));
+      std::vector<T> Fr((size_t)L.ncells * J * d * nl * R4, T(0)), Hr((size_t)L.ncells * J * C * R4, T(0));
+#pragma omp parallel for schedule(static)
+      for (int64_t cl = 0; cl < L.ncells; ++cl) {
+        for (int j = 0; j < J; ++j) {
+          const bool cpx = j >= V.te.nreal;
+          T* X = &A[(size_t)cl * aw + (size_t)(j < V.te.nreal ? j : 2 * j - V.te.nreal) * mp * mp];
+          const std::complex<double>* Ai = &V.Ainv[((size_t)cl * J + j) * nl * nl];
+          for (int row = 0; row < nl; ++row)
+            for (int k = 0; k < nl; ++k) {
+              const std::complex<double> z = Ai[(size_t)row * nl + k];
+              X[vanka_swizzle_index(mp, row, k)] = (T)z.real();
+              if (cpx) X[(size_t)mp * mp + vanka_swizzle_index(mp, row, k)] = (T)z.imag();
+            }
+          const std::complex<double>* F = &V.F[((size_t)cl * J + j) * d * nl * C];
+          for (int ci = 0; ci < d * nl; ++ci)
+            for (int l = 0; l < C; ++l) {
+              T* f = &Fr[(((size_t)cl * J + j) * d * nl + ci) * R4 + 2 * l];
+              f[0] = (T)F[(size_t)ci * C + l].real();
+              f[1] = (T)F[(size_t)ci * C + l].imag();
+            }
+          const std::complex<double>* Hi = &V.Hinv[((size_t)cl * J + j) * C * C];
+          for (int l = 0; l < C; ++l)
+            for (int l2 = 0; l2 < C; ++l2) {
+              T* h = &Hr[(((size_t)cl * J + j) * C + l) * R4 + 2 * l2];
+              h[0] = (T)Hi[(size_t)l * C + l2].real();
+              h[1] = (T)Hi[(size_t)l * C + l2].imag();
+            }
+        }
+      }
+      D.Asw = c->pool.upload<T>(A, s);
+      D.Bm = c->pool.upload<T>(V.Bm, s);
+      D.F = c->pool.upload<T>(Fr, s);
+      D.Hinv = c->pool.upload<T>(Hr, s);
+    } else if (with_vanka && l + 1 < nlev) {
       const VankaFactors& V = VF[l];
       D.coef = c->pool.upload<T>(V.coef, s);
-      if (c->p.vanka_mode == STMG_VANKA_DENSE) {
+      if (D.vform == STMG_VANKA_DENSE) {
         D.dense = c->pool.upload<T>(dense[l], s);
       } else {
         // A_s^{-1} in MFMA operand order, padded to a multiple of 16
@@ -307,9 +399,12 @@ template <typename T>
 void op_vanka_with(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x, T* E, bool xzero) {
   // xzero: x holds no values yet and starts at 0
   T om = (T)c->p.omega;
-  if (c->p.vanka_mode == STMG_VANKA_DENSE) {
+  if (D.vform == STMG_VANKA_DENSE) {
     if (xzero) HIPCHK(launch_fill<T>(x, T(0), D.ndofs, c->stream));
     HIPCHK(launch_vanka_dense<T>(D.a, D.dense, r, x, om, c->stream));
+  } else if (D.vform == STMG_VANKA_DECOUPLED || D.vform == kFormDiagonal) {
+    HIPCHK(launch_vanka_decoupled<T>(D.a, D.Asw, D.Bm, D.F, D.Hinv, D.coef, r, x, om, E, c->stream, true, xzero,
+                                     D.vform == kFormDiagonal));
   } else {
     HIPCHK(launch_vanka_factored<T>(D.a, D.Asw, D.Bm, D.F, D.Hinv, D.coef, r, x, om, E, c->stream, true, xzero));
   }
@@ -598,7 +693,7 @@ stmg_status stmg_default_params(stmg_params* p) {
   p->dim = 3; p->n_cells_1d = 4; p->n_coarse_1d = 2; p->deform_amp = 0.0;
   p->r = 1; p->k = 1; p->n_sub = 2; p->tau = 0.05; p->nu = 1.0;
   p->r_min = 1; p->k_min = 1; p->time_h_coarsening = 0; p->placement = 0; p->nu_pre = 1; p->nu_post = 1; p->omega = 0.8;
-  p->precision = STMG_FP64; p->vanka_mode = STMG_VANKA_FACTORED; p->device = 0; p->stream = nullptr;
+  p->precision = STMG_FP64; p->vanka_mode = STMG_VANKA_AUTO; p->device = 0; p->stream = nullptr;
   return STMG_OK;
 }
 
@@ -615,7 +710,8 @@ static int check_params(const stmg_params* p, std::string& msg) {
   if (!(p->tau > 0) || !(p->nu > 0 || p->nu_fn)) { msg = "tau and nu must be positive"; return STMG_EINVAL; }
   if (!(p->omega > 0) || p->nu_pre < 0 || p->nu_post < 0) { msg = "bad smoother parameters"; return STMG_EINVAL; }
   if (p->precision != STMG_FP64 && p->precision != STMG_MIXED_FP32) { msg = "bad precision"; return STMG_EINVAL; }
-  if (p->vanka_mode != STMG_VANKA_FACTORED && p->vanka_mode != STMG_VANKA_DENSE) { msg = "bad vanka_mode"; return STMG_EINVAL; }
+  if (p->vanka_mode < STMG_VANKA_FACTORED || p->vanka_mode > STMG_VANKA_AUTO) { msg = "bad vanka_mode"; return STMG_EINVAL; }
+  if (p->local_solver != STMG_LOCAL_EXACT && p->local_solver != STMG_LOCAL_DIAGONAL) { msg = "bad local_solver"; return STMG_EINVAL; }
   if (p->placement != 0 && p->placement != 1) { msg = "bad placement"; return STMG_EINVAL; }
   return STMG_OK;
 }
@@ -664,10 +760,16 @@ stmg_status stmg_setup(const stmg_params* p, stmg_ctx** out) {
     c->host.resize(specs.size());
     for (size_t l = 0; l < specs.size(); ++l) build_level(P, specs[l], c->host[l]);
     std::vector<VankaFactors> VF(specs.size());
+    std::vector<VankaDecoupled> VD(specs.size());
     std::vector<std::vector<double>> dense(specs.size());
     for (size_t l = 0; l + 1 < specs.size(); ++l) {
+      const int form = vanka_form(*p, c->host[l]);
+      if (form == STMG_VANKA_DECOUPLED || form == kFormDiagonal) {
+        vanka_decoupled(c->host[l], VD[l], nthreads, form == kFormDiagonal);
+        continue;
+      }
       vanka_factors(c->host[l], VF[l], nthreads);
-      if (p->vanka_mode == STMG_VANKA_DENSE) vanka_dense(c->host[l], VF[l], dense[l], nthreads);
+      if (form == STMG_VANKA_DENSE) vanka_dense(c->host[l], VF[l], dense[l], nthreads);
     }
     std::vector<double> cinv, cg;
     coarse_inverse(c->host.back(), cinv, cg);
@@ -678,8 +780,8 @@ stmg_status stmg_setup(const stmg_params* p, stmg_ctx** out) {
     c->volume0 = c->host[0].volume;
     // the FP64 hierarchy always exists (operator, per-op calls); it holds the
     // smoother factors only in FP64 mode
-    build_hier<double>(c, c->H64, VF, dense, !c->mixed);
-    if (c->mixed) build_hier<float>(c, c->H32, VF, dense, true);
+    build_hier<double>(c, c->H64, VF, dense, VD, !c->mixed);
+    if (c->mixed) build_hier<float>(c, c->H32, VF, dense, VD, true);
     int64_t ns = (int64_t)c->host[0].N * c->host[0].nt;
     c->partial = c->pool.alloc<double>((ns + 128) * 520 + 1024 * 128);
     c->dh = c->pool.alloc<double>(1024);
@@ -864,7 +966,8 @@ stmg_status stmg_kernel_time(stmg_ctx* c, int which, int level, int reps, double
   if (!c || !avg_ms || reps < 1 || level < 0 || level >= (int)c->host.size()) return STMG_EINVAL;
   if (which == 0 && level + 1 >= (int)c->host.size()) return STMG_EINVAL;
   if (which < 0 || which > 3) return STMG_EINVAL;
-  if (which == 2 && (level + 1 >= (int)c->host.size() || c->p.vanka_mode != STMG_VANKA_FACTORED)) return STMG_EINVAL;
+  if (which == 2 && (level + 1 >= (int)c->host.size() || vanka_form(c->p, c->host[level]) == STMG_VANKA_DENSE))
+    return STMG_EINVAL;
   return (stmg_status)guarded(c, [&] {
     auto run = [&](auto& D) {
       using T = std::remove_reference_t<decltype(*D.x)>;
@@ -878,6 +981,9 @@ stmg_status stmg_kernel_time(stmg_ctx* c, int which, int level, int reps, double
       for (int i = 0; i < reps; ++i) {
         if (which == 0) op_vanka<T>(c, D, D.r, D.x);
         else if (which == 1) op_apply<T>(c, D, D.x, D.b, D.r, 1);
+        else if (which == 2 && (D.vform == STMG_VANKA_DECOUPLED || D.vform == kFormDiagonal))
+          HIPCHK(launch_vanka_decoupled<T>(D.a, D.Asw, D.Bm, D.F, D.Hinv, D.coef, D.r, D.x, (T)c->p.omega, D.E,
+                                           c->stream, false, false, D.vform == kFormDiagonal));
         else if (which == 2)
           HIPCHK(launch_vanka_factored<T>(D.a, D.Asw, D.Bm, D.F, D.Hinv, D.coef, D.r, D.x, (T)c->p.omega, D.E,
                                           c->stream, false));
@@ -1117,6 +1223,97 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
   if (rc != STMG_OK) return (stmg_status)rc;
   if (status != STMG_OK) c->err = "FGMRES did not reach the tolerance within max_it";
   return (stmg_status)status;
+}
+
+// ------------------------------------------------------------ time marching
+stmg_status stmg_time_nodes(const stmg_ctx* c, double* t_hat) {
+  if (!c || !t_hat) return STMG_EINVAL;
+  const LevelHost& L = c->host[0];
+  for (int a = 0; a < L.nt; ++a) t_hat[a] = L.td.t[a];
+  return STMG_OK;
+}
+
+// b = f - S_full gD - C^1 v0 on free rows, 0 on Dirichlet rows, where gD
+// holds g's Dirichlet velocity entries and zeros elsewhere (f, g, v0 may be null)
+static void slab_rhs_impl(stmg_ctx* c, const double* f, const double* v0, const double* g, double* b) {
+  DevLevel<double>& D = c->H64.L[0];
+  const int64_t n = D.ndofs;
+  if (!c->slab_b) {
+    c->slab_b = c->pool.alloc<double>(n);
+    c->slab_g = c->pool.alloc<double>(n);
+  }
+  HIPCHK(launch_fill<double>(c->slab_g, 0.0, n, c->stream));
+  if (g) HIPCHK(launch_set_dirichlet(D.a, g, c->slab_g, c->stream));
+  const double* fz = f;
+  if (!fz) {  // zero forcing
+    HIPCHK(launch_fill<double>(b, 0.0, n, c->stream));
+    fz = b;
+  }
+  HIPCHK(launch_slab_rhs(D.a, D.geo, D.tab, fz, c->slab_g, v0, b, D.E, c->stream));
+}
+
+stmg_status stmg_slab_rhs(stmg_ctx* c, const double* f, const double* v0, const double* g, double* b) {
+  if (!c || !b) return STMG_EINVAL;
+  return (stmg_status)guarded(c, [&] {
+    slab_rhs_impl(c, f, v0, g, b);
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+stmg_status stmg_slab_end_value(stmg_ctx* c, const double* x, double* v_end) {
+  if (!c || !x || !v_end) return STMG_EINVAL;
+  return (stmg_status)guarded(c, [&] {
+    const LevelHost& L = c->host[0];
+    const double* src = x + (int64_t)(L.N - 1) * L.slab + (int64_t)(L.nt - 1) * L.Mv;
+    HIPCHK(hipMemcpyAsync(v_end, src, (size_t)L.Mv * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  });
+}
+
+stmg_status stmg_solve_slab(stmg_ctx* c, const double* f, const double* v0, const double* g, double* x, double rtol,
+                            int max_it, stmg_solve_info* info) {
+  if (!c || !x || !(rtol > 0) || max_it < 1) return STMG_EINVAL;
+  int rc = guarded(c, [&] {
+    const int64_t n = c->host[0].ndofs;
+    if (!c->slab_b) {
+      c->slab_b = c->pool.alloc<double>(n);
+      c->slab_g = c->pool.alloc<double>(n);
+    }
+    slab_rhs_impl(c, f, v0, g, c->slab_b);
+  });
+  if (rc != STMG_OK) return (stmg_status)rc;
+  // the homogeneous system for x - gD, then the Dirichlet values
+  const stmg_status st = stmg_solve(c, c->slab_b, x, rtol, max_it, info);
+  if (st != STMG_OK && st != STMG_ENOCONV) return st;
+  if (g) {
+    rc = guarded(c, [&] {
+      HIPCHK(launch_set_dirichlet(c->H64.L[0].a, g, x, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+    });
+    if (rc != STMG_OK) return (stmg_status)rc;
+  }
+  return st;
+}
+
+stmg_status stmg_march(stmg_ctx* c, int n_slabs, const double* f, const double* g, const double* v0, double* x,
+                       double rtol, int max_it, int* iterations) {
+  if (!c || !x || n_slabs < 1 || !(rtol > 0) || max_it < 1) return STMG_EINVAL;
+  const LevelHost& L = c->host[0];
+  const int64_t n = L.ndofs;
+  for (int s = 0; s < n_slabs; ++s) {
+    // the previous slab's end value: the last temporal dof (the Radau point
+    // at the right end) of its last subinterval
+    const double* vin = s == 0 ? v0 : x + (s - 1) * n + (int64_t)(L.N - 1) * L.slab + (int64_t)(L.nt - 1) * L.Mv;
+    stmg_solve_info info;
+    const stmg_status st = stmg_solve_slab(c, f ? f + s * n : nullptr, vin, g ? g + s * n : nullptr, x + s * n,
+                                           rtol, max_it, &info);
+    if (iterations) iterations[s] = info.iterations;
+    if (st != STMG_OK) {
+      if (st == STMG_ENOCONV) c->err = "slab " + std::to_string(s) + ": FGMRES did not reach the tolerance";
+      return st;
+    }
+  }
+  return STMG_OK;
 }
 
 stmg_status stmg_learned_load(stmg_ctx* c, const float* w, size_t n) {

@@ -20,7 +20,8 @@ STATUS = {0: "STMG_OK", -1: "STMG_EINVAL", -2: "STMG_ENOMEM", -3: "STMG_EDEVICE"
           -5: "STMG_ESINGULAR", -6: "STMG_EUNSUPPORTED"}
 FP64, MIXED_FP32 = 0, 1
 OPT_APPLY_SUBINTERVALS, OPT_NET_CHUNK = 1, 2  # stmg_option
-VANKA_FACTORED, VANKA_DENSE = 0, 1
+VANKA_FACTORED, VANKA_DENSE, VANKA_DECOUPLED, VANKA_AUTO = 0, 1, 2, 3
+LOCAL_EXACT, LOCAL_DIAGONAL = 0, 1
 
 NU_FN = ctypes.CFUNCTYPE(None, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                          ctypes.c_void_p)
@@ -34,7 +35,8 @@ class Params(ctypes.Structure):
                 ("k_min", ctypes.c_int), ("time_h_coarsening", ctypes.c_int), ("placement", ctypes.c_int),
                 ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("omega", ctypes.c_double), ("precision", ctypes.c_int),
-                ("vanka_mode", ctypes.c_int), ("device", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("vanka_mode", ctypes.c_int), ("local_solver", ctypes.c_int), ("device", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -69,6 +71,12 @@ _sig = {
     "stmg_vcycle": [_P, _P, _P],
     "stmg_solve": [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.POINTER(SolveInfo)],
     "stmg_project_pressure_mean_zero": [_P, _P],
+    "stmg_time_nodes": [_P, _D],
+    "stmg_slab_rhs": [_P, _P, _P, _P, _P],
+    "stmg_slab_end_value": [_P, _P, _P],
+    "stmg_solve_slab": [_P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.POINTER(SolveInfo)],
+    "stmg_march": [_P, ctypes.c_int, _P, _P, _P, _P, ctypes.c_double, ctypes.c_int,
+                   ctypes.POINTER(ctypes.c_int)],
     "stmg_learned_load": [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t],
     "stmg_learned_weights": [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t],
     "stmg_learned_enable": [_P, ctypes.c_int],
@@ -236,6 +244,46 @@ class Solver:
 
     def project_pressure(self, x):
         _check(lib.stmg_project_pressure_mean_zero(self.ctx, _ptr(x, self.ndofs(0))), self.ctx)
+
+    # ------------------------------------------------------- time marching
+    def time_nodes(self):
+        import numpy as np
+        t = np.zeros(self.params.k + 1)
+        _check(lib.stmg_time_nodes(self.ctx, t.ctypes.data_as(_D)), self.ctx)
+        return t
+
+    @staticmethod
+    def _optr(t, n):
+        return ctypes.c_void_p(None) if t is None else _ptr(t, n)
+
+    def slab_rhs(self, b, f=None, v0=None, g=None):
+        n = self.ndofs(0)
+        nv = self.sizes(0)[1]
+        _check(lib.stmg_slab_rhs(self.ctx, self._optr(f, n), self._optr(v0, nv), self._optr(g, n), _ptr(b, n)),
+               self.ctx)
+
+    def slab_end_value(self, x):
+        n, nv = self.ndofs(0), self.sizes(0)[1]
+        v = torch.empty(nv, dtype=torch.float64, device="cuda")
+        _check(lib.stmg_slab_end_value(self.ctx, _ptr(x, n), _ptr(v, nv)), self.ctx)
+        return v
+
+    def solve_slab(self, x, f=None, v0=None, g=None, rtol=1e-8, max_it=100):
+        n, nv = self.ndofs(0), self.sizes(0)[1]
+        info = SolveInfo()
+        _check(lib.stmg_solve_slab(self.ctx, self._optr(f, n), self._optr(v0, nv), self._optr(g, n), _ptr(x, n),
+                                   rtol, max_it, ctypes.byref(info)), self.ctx)
+        return dict(iterations=info.iterations, rel_residual=info.rel_residual, t_solve_s=info.t_solve_s)
+
+    def march(self, n_slabs, x, f=None, g=None, v0=None, rtol=1e-8, max_it=100):
+        """x, f, g: (n_slabs * n_dofs) device arrays; returns the iterations per slab."""
+        import numpy as np
+        n, nv = self.ndofs(0), self.sizes(0)[1]
+        its = np.zeros(n_slabs, dtype=np.int32)
+        _check(lib.stmg_march(self.ctx, n_slabs, self._optr(f, n * n_slabs), self._optr(g, n * n_slabs),
+                              self._optr(v0, nv), _ptr(x, n * n_slabs), rtol, max_it,
+                              its.ctypes.data_as(ctypes.POINTER(ctypes.c_int))), self.ctx)
+        return its
 
     # ---------------------------------------------------------- learned
     def learned_load(self, weights):

@@ -131,3 +131,24 @@ class Manufactured2D:
               + nu * 2 * pi ** 3 * st * np.sin(2 * X) * (2 * np.cos(2 * Y) - 1)
               + st * 0.5 * pi * np.sin(2 * X) * np.cos(2 * Y))
         return np.stack([f1, f2], axis=1)
+
+
+# ------------------------------------------------------------ lid-driven cavity
+def lid_dirichlet(d, n, r, k, N, tau, t0, t_hat):
+    """Dirichlet values of the lid-driven cavity for one slab (layout above):
+    on the lid (the face x_{d-1} = 1, its edges included) the first velocity
+    component is sin(pi t / 4), every other Dirichlet value is 0 (no-slip
+    walls); free entries and pressure are 0.  Temporal dof a of subinterval
+    s sits at t0 + tau (s + (t_hat[a] + 1) / 2), t_hat the DG(k) nodes on
+    (-1, 1] (the caller supplies them)."""
+    lay = layout(d, n, r, k, N)
+    nn = lay["nn"]
+    lid = np.zeros(lay["nodes"], dtype=bool)
+    lid.reshape([nn] * d)[nn - 1] = True          # first axis is x_{d-1}
+    g = np.zeros(lay["ndofs"])
+    for s in range(N):
+        for a in range(k + 1):
+            t = t0 + tau * (s + 0.5 * (t_hat[a] + 1.0))
+            o = s * lay["slab"] + a * lay["Mv"]
+            g[o:o + lay["nodes"]] = np.where(lid, np.sin(np.pi * t / 4.0), 0.0)
+    return g

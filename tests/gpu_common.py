@@ -52,14 +52,14 @@ def make_solver(cfg, **over):
 
 
 @functools.lru_cache(maxsize=None)
-def oracle_mg(name):
+def oracle_mg(name, smoother="exact"):
     from oracle.mg import Multigrid
     cfg = CONFIGS[name]
     nf = nu_field(cfg)
     return Multigrid(cfg["dim"], cfg["n_cells_1d"], cfg["r"], cfg["k"], cfg["n_sub"], TAU,
                      nu=nf if nf is not None else 1.0, amp=cfg["deform_amp"], n_coarse=cfg["n_coarse_1d"],
                      k_min=cfg["k_min"], omega=OMEGA, time_h=cfg.get("time_h_coarsening", 0) == 1,
-                     placement="top" if cfg.get("placement", 0) == 1 else "paper")
+                     placement="top" if cfg.get("placement", 0) == 1 else "paper", smoother=smoother)
 
 
 def rhs(cfg, seed):

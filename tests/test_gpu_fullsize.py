@@ -113,12 +113,15 @@ def correction_samples(S, rng):
     return np.array(rows)
 
 
-@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+@pytest.mark.parametrize("prec", ["mixed", "fp64", "mixed_coupled"])
 def test_fullsize_smoother_correction(nu, oracle_level, prec):
+    """Decoupled local solves (the default) in the mixed and FP64 contexts,
+    and the Schur-factored space-time form in the mixed context."""
     from paper_2502_09159_amd import stmg
     S = oracle_level
-    p = stmg.MIXED_FP32 if prec == "mixed" else stmg.FP64
-    g = stmg.Solver(nu_fn=nu, precision=p, **C5)
+    p = stmg.FP64 if prec == "fp64" else stmg.MIXED_FP32
+    mode = stmg.VANKA_FACTORED if prec == "mixed_coupled" else stmg.VANKA_DECOUPLED
+    g = stmg.Solver(nu_fn=nu, precision=p, vanka_mode=mode, **C5)
     try:
         r = random_rhs(3, 32, 2, 1, 8, 52)
         rng = np.random.default_rng(53)
@@ -134,7 +137,7 @@ def test_fullsize_smoother_correction(nu, oracle_level, prec):
         ref = np.array([S.correction_entry(r, i) for i in rows])
         err = np.linalg.norm(u[rows] - ref) / np.linalg.norm(ref)
         announce(f"C5 full size: smoother correction ({prec}), {len(rows)} sampled entries, rel L2 error {err:.2e}")
-        assert err <= (1e-5 if prec == "mixed" else 1e-12)
+        assert err <= (1e-12 if prec == "fp64" else 1e-5)
     finally:
         g.close()
 

@@ -87,3 +87,42 @@ def test_wrong_pressure_head_is_caught(monkeypatch):
     ref = pins.hand_built_learned(r_, Ws, 2, 2)
     monkeypatch.setattr(ln, "head", lambda y, mask: (y[:, :6, :] * (1.0 - mask[:, None, :]), y[:, 6:, 0]))
     assert pins.rel(ln.correction(L, Ws, r_), ref) > CAUGHT
+
+
+def _march_cases():
+    import test_oracle_marching as tm
+    return tm, tm.CASES[0]
+
+
+def test_wrong_sign_of_the_previous_slab_term_is_caught(monkeypatch):
+    """C^1 V_0 entered with the wrong sign breaks reproduction and chaining."""
+    import oracle.marching as mr
+    tm, c = _march_cases()
+    orig = mr.full_apply
+
+    def flipped(L, x, v0=None):
+        return orig(L, x, None if v0 is None else -v0)
+
+    monkeypatch.setattr(mr, "full_apply", flipped)
+    with pytest.raises(AssertionError):
+        tm.test_constant_flow_is_reproduced(c)
+    with pytest.raises(AssertionError):
+        tm.test_two_slabs_equal_one_slab_of_twice_the_length(c)
+
+
+def test_dropped_dirichlet_columns_in_the_lifting_are_caught(monkeypatch):
+    """Lifting with the homogeneous operator (Dirichlet columns zero) loses
+    the boundary data's coupling into the free rows."""
+    import oracle.marching as mr
+    tm, c = _march_cases()
+
+    def homogeneous(L, x, v0=None):
+        y = L.apply(x)
+        if v0 is not None:
+            for a in range(L.nt):
+                y[L.v_index(0, a)] -= L.Ctau[a, -1] * (L.sp.Mh @ v0)
+        return y
+
+    monkeypatch.setattr(mr, "full_apply", homogeneous)
+    with pytest.raises(AssertionError):
+        tm.test_linear_in_time_flow_is_reproduced(c)
