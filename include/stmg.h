@@ -136,11 +136,16 @@ const char* stmg_last_error(const stmg_ctx* ctx);
  *    (InAlg) in registers (0 = automatic: all N unless the grid would not
  *    fill the chip; values are clamped to [1, N]);
  *  STMG_OPT_NET_CHUNK: space-time cells per inference chunk of the learned
- *    correction (0 = default 65536; at most 65536).
- * Returns STMG_EINVAL for an unknown option or a negative value. */
+ *    correction (0 = default 65536; at most 65536);
+ *  STMG_OPT_APPLY_LOOP_ORDER: loop order of the operator's cell kernel on 3D
+ *    FP32 levels (0 = automatic: components inner; 1 = components outer, one
+ *    component's geometry live at a time; 2 = components inner, the pressure
+ *    and continuity rows shared by the components).
+ * Returns STMG_EINVAL for an unknown option or value. */
 typedef enum {
   STMG_OPT_APPLY_SUBINTERVALS = 1,
-  STMG_OPT_NET_CHUNK = 2
+  STMG_OPT_NET_CHUNK = 2,
+  STMG_OPT_APPLY_LOOP_ORDER = 3
 } stmg_option;
 stmg_status stmg_set_option(stmg_ctx* ctx, int option, int64_t value);
 

@@ -202,7 +202,11 @@ __device__ __forceinline__ void pencil(const T (&v)[ZP], T (&o)[ZP], int mat, co
 // every node), and for the first subinterval the jump term takes the end
 // value v0 of the previous slab (d x nodes, or none): y = b - S_full x - C^1 v0
 // on free rows, the lifting of inhomogeneous Dirichlet data (Eq. (AlgSysTMS)).
-template <typename T, int D, int Q, int NT, bool FULL = false>
+// CI (3D): the components are the inner loop, so the pressure at the Gauss
+// points, the continuity-row reduction and its store are done once per
+// (subinterval, temporal dof) instead of once per component; all components'
+// metric, nodal values and jump values stay in registers.
+template <typename T, int D, int Q, int NT, bool FULL = false, bool CI = false>
 __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict__ geo, const T* __restrict__ tab,
                                                const T* __restrict__ x, const T* __restrict__ b,
                                                T* __restrict__ y, T* __restrict__ E, int mode, int nper,
@@ -311,6 +315,149 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
       pencil<1, Q, ZP>(w, uq, 0, sCY, qy * 4, tS);
     }
   };
+
+  if constexpr (CI) {
+    static_assert(D == 3, "components-inner evaluation is for 3D levels");
+    // geometry: JxW, nu JxW J^-1 J^-T, and every column of JxW J^-1
+    T jw[ZP], gm[NS][ZP], ja[D][D][ZP];  // ja[comp][j][z]
+#pragma unroll
+    for (int z = 0; z < ZP; ++z) {
+      jw[z] = gc[z];
+#pragma unroll
+      for (int comp = 0; comp < D; ++comp)
+#pragma unroll
+        for (int j = 0; j < D; ++j) ja[comp][j][z] = gc[(1 + j * D + comp) * 16 * ZP + z];
+#pragma unroll
+      for (int t = 0; t < NS; ++t) gm[t][z] = gc[(1 + D * D + t) * 16 * ZP + z];
+    }
+    T up[D][ZP];
+#pragma unroll
+    for (int comp = 0; comp < D; ++comp) {
+      if (n0 > 0 && n0 < n1) interp(n0 - 1, NT - 1, comp, up[comp]);
+      else
+#pragma unroll
+        for (int z = 0; z < ZP; ++z) up[comp][z] = 0;
+    }
+    for (int n = n0; n < n1; ++n) {
+      T uq[D][NT][ZP];
+#pragma unroll
+      for (int comp = 0; comp < D; ++comp)
+#pragma unroll
+        for (int bb = 0; bb < NT; ++bb) interp(n, bb, comp, uq[comp][bb]);
+      // temporal dofs one at a time; uq[comp] is rotated so that uq[comp][0]
+      // holds dof a and uq[comp][j] dof (a + j) mod NT
+#pragma unroll 1
+      for (int a = 0; a < NT; ++a) {
+        const T ca = tcoef[a];
+        const int64_t prow = (int64_t)n * L.slab + (int64_t)NT * L.Mv + (int64_t)a * L.Mp + cell * C;
+        const T prev_in = mode ? b[prow + min(lane16, C - 1)] : T(0);
+        T pres[ZP];
+        {
+          const T* ps = x + prow + opaque_v(0);
+          T pl[C];
+#pragma unroll
+          for (int l = 0; l < C; ++l) {
+            const T v = ps[l];
+            pl[l] = cvalid ? v : T(0);
+          }
+          const int pr = opaque_v(po);
+#pragma unroll
+          for (int z = 0; z < ZP; ++z) {
+            T s = 0;
+#pragma unroll
+            for (int l = 0; l < C; ++l) s += sPsi[pr + (z * C + l) * 16] * pl[l];
+            pres[z] = s;
+          }
+        }
+        T dvs[ZP];
+#pragma unroll
+        for (int z = 0; z < ZP; ++z) dvs[z] = 0;
+#pragma unroll
+        for (int comp = 0; comp < D; ++comp) {
+          T Zq[ZP];
+#pragma unroll
+          for (int z = 0; z < ZP; ++z) {
+            T w = -tphi[a] * up[comp][z];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+              const int bb = a + j < NT ? a + j : a + j - NT;
+              w += tK[a * NT + bb] * uq[comp][j][z];
+            }
+            Zq[z] = w * jw[z];
+          }
+          T g[3][ZP];
+          pencil<0, Q, ZP>(uq[comp][0], g[0], 1, sCX, 16 + qx * 4, tS);
+          pencil<1, Q, ZP>(uq[comp][0], g[1], 1, sCY, 16 + qy * 4, tS);
+          pencil<2, Q, ZP>(uq[comp][0], g[2], 1, sCX, 0, tS);
+#pragma unroll
+          for (int z = 0; z < ZP; ++z) {
+            T gr[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) gr[j] = g[j][z];
+            T dsum = 0;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+              T s = 0;
+#pragma unroll
+              for (int k = 0; k < D; ++k) {
+                const int t = j <= k ? j * D - j * (j - 1) / 2 + (k - j) : k * D - k * (k - 1) / 2 + (j - k);
+                s += gm[t][z] * gr[k];
+              }
+              g[j][z] = ca * (s - pres[z] * ja[comp][j][z]);
+              dsum += ja[comp][j][z] * gr[j];
+            }
+            dvs[z] -= ca * dsum;
+          }
+          T t1[ZP];
+          pencil<0, Q, ZP>(g[0], t1, 3, sCX, 48 + qx * 4, tS);
+#pragma unroll
+          for (int z = 0; z < ZP; ++z) Zq[z] += t1[z];
+          pencil<1, Q, ZP>(g[1], t1, 3, sCY, 48 + qy * 4, tS);
+#pragma unroll
+          for (int z = 0; z < ZP; ++z) Zq[z] += t1[z];
+          pencil<2, Q, ZP>(g[2], t1, 3, sCX, 0, tS);
+#pragma unroll
+          for (int z = 0; z < ZP; ++z) Zq[z] += t1[z];
+          pencil<0, Q, ZP>(Zq, t1, 2, sCX, 32 + qx * 4, tS);
+          pencil<1, Q, ZP>(t1, Zq, 2, sCY, 32 + qy * 4, tS);
+          pencil<2, Q, ZP>(Zq, t1, 2, sCX, 0, tS);
+          if (lvalid) {
+            T* Eo = Ec + ((int64_t)(n * NT + a) * D + comp) * NE;
+#pragma unroll
+            for (int z = 0; z < ZP; ++z) Eo[(int64_t)W * W * z] = t1[z];
+          }
+        }
+        // continuity rows of dof a, all components at once
+        {
+          const int pr = opaque_v(po);
+          T mine = 0;
+#pragma unroll
+          for (int l = 0; l < C; ++l) {
+            T s = 0;
+#pragma unroll
+            for (int z = 0; z < ZP; ++z) s += sPsi[pr + (z * C + l) * 16] * dvs[z];
+            s = row_sum16(s);
+            if (lane16 == l) mine = s;
+          }
+          if (cvalid && lane16 < C) y[prow + lane16] = mode ? prev_in - mine : mine;
+        }
+#pragma unroll
+        for (int comp = 0; comp < D; ++comp)
+#pragma unroll
+          for (int z = 0; z < ZP; ++z) {
+            const T first = uq[comp][0][z];
+#pragma unroll
+            for (int j = 0; j + 1 < NT; ++j) uq[comp][j][z] = uq[comp][j + 1][z];
+            uq[comp][NT - 1][z] = first;
+          }
+      }
+#pragma unroll
+      for (int comp = 0; comp < D; ++comp)
+#pragma unroll
+        for (int z = 0; z < ZP; ++z) up[comp][z] = uq[comp][NT - 1][z];
+    }
+    return;
+  }
 
 #pragma unroll 1
   for (int comp = 0; comp < D; ++comp) {
@@ -645,7 +792,7 @@ static hipError_t node_gather(const LevelArgs& L, const T* E, const T* xin, cons
 
 template <typename T, int D, int Q, int NT>
 static hipError_t apply_impl(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y,
-                             int mode, T* E, hipStream_t s, bool gather, int nper_req) {
+                             int mode, T* E, hipStream_t s, bool gather, int nper_req, int variant) {
   constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
   if (L.C != C || L.nt != NT || L.Q != Q || L.nodes >= (int64_t(1) << 31)) return hipErrorInvalidValue;
   const int64_t ncells = L.Mp / L.C;
@@ -655,7 +802,17 @@ static hipError_t apply_impl(const LevelArgs& L, const T* geo, const T* tab, con
   if (nper_req > 0) nchunk = (L.N + std::min(nper_req, L.N) - 1) / std::min(nper_req, L.N);
   const int nper = (int)((L.N + nchunk - 1) / nchunk);
   nchunk = (L.N + nper - 1) / nper;
-  k_apply<T, D, Q, NT><<<dim3((unsigned)nbx, (unsigned)nchunk), 256, 0, s>>>(L, geo, tab, x, b, y, E, mode, nper);
+  // FP32 3D levels: components inner unless asked otherwise (fewer
+  // instructions); FP64 keeps the components outer (its registers would not fit)
+  if constexpr (D == 3 && sizeof(T) == 4) {
+    if (variant != 1)
+      k_apply<T, D, Q, NT, false, true><<<dim3((unsigned)nbx, (unsigned)nchunk), 256, 0, s>>>(L, geo, tab, x, b, y, E,
+                                                                                            mode, nper);
+    else
+      k_apply<T, D, Q, NT><<<dim3((unsigned)nbx, (unsigned)nchunk), 256, 0, s>>>(L, geo, tab, x, b, y, E, mode, nper);
+  } else {
+    k_apply<T, D, Q, NT><<<dim3((unsigned)nbx, (unsigned)nchunk), 256, 0, s>>>(L, geo, tab, x, b, y, E, mode, nper);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !gather) return e;
   return node_gather<T, 0>(L, E, x, b, y, mode, T(0), s);
@@ -663,9 +820,10 @@ static hipError_t apply_impl(const LevelArgs& L, const T* geo, const T* tab, con
 
 template <typename T>
 hipError_t launch_apply(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y, int mode,
-                        T* E, hipStream_t s, bool gather, int nper) {
+                        T* E, hipStream_t s, bool gather, int nper, int variant) {
 #define STMG_AP(DD, QQ, NN) \
-  if (L.d == DD && L.Q == QQ && L.nt == NN) return apply_impl<T, DD, QQ, NN>(L, geo, tab, x, b, y, mode, E, s, gather, nper);
+  if (L.d == DD && L.Q == QQ && L.nt == NN)                                                    \
+    return apply_impl<T, DD, QQ, NN>(L, geo, tab, x, b, y, mode, E, s, gather, nper, variant);
   STMG_AP(2, 3, 1) STMG_AP(2, 3, 2) STMG_AP(2, 3, 3) STMG_AP(2, 3, 4)
   STMG_AP(2, 4, 1) STMG_AP(2, 4, 2) STMG_AP(2, 4, 3) STMG_AP(2, 4, 4)
   STMG_AP(3, 3, 1) STMG_AP(3, 3, 2) STMG_AP(3, 3, 3) STMG_AP(3, 3, 4)
@@ -2511,7 +2669,7 @@ hipError_t launch_project_pressure(const LevelArgs& L, const double* mom, double
 // explicit instantiations
 #define STMG_INST(T)                                                                                                \
   template hipError_t launch_apply<T>(const LevelArgs&, const T*, const T*, const T*, const T*, T*, int, T*,      \
-                                      hipStream_t, bool, int);                                                      \
+                                      hipStream_t, bool, int, int);                                                 \
   template hipError_t launch_vanka_factored<T>(const LevelArgs&, const T*, const T*, const T*, const T*, const T*, \
                                                const T*, T*, T, T*, hipStream_t, bool, bool);                       \
   template hipError_t launch_vanka_dense<T>(const LevelArgs&, const T*, const T*, T*, T, hipStream_t);             \

@@ -40,9 +40,11 @@ template <typename T>
 // gather = false runs the cell kernel only (E written, y's pressure rows
 // written, velocity rows untouched): for timing.
 // nper > 0 fixes the subintervals one wave walks through (clamped to [1, N]);
-// 0 picks them so that the grid fills the chip.
+// 0 picks them so that the grid fills the chip.  variant: 0 automatic, 1 the
+// components as the outer loop of the cell kernel, 2 as the inner loop (3D
+// FP32 only; elsewhere the outer loop is used).
 hipError_t launch_apply(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y, int mode,
-                        T* E, hipStream_t s, bool gather = true, int nper = 0);
+                        T* E, hipStream_t s, bool gather = true, int nper = 0, int variant = 0);
 
 // Slab right-hand side for time marching (Eq. (AlgSysTMS)) with lifted
 // Dirichlet data, FP64: out = f - S_full g - C^1 v0 on free velocity rows and

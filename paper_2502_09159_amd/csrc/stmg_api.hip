@@ -166,6 +166,7 @@ struct stmg_ctx {
   double *slab_b = nullptr, *slab_g = nullptr;
   // execution options (stmg_set_option)
   int opt_apply_nper = 0;      // subintervals per wave of the operator's cell kernel (0: automatic)
+  int opt_apply_variant = 0;   // loop order of the operator's cell kernel (0: automatic)
   int64_t opt_net_chunk = 0;   // space-time cells per inference chunk (0: the default)
 };
 
@@ -390,7 +391,8 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
 // ------------------------------------------------------------- level ops
 template <typename T>
 void op_apply(stmg_ctx* c, DevLevel<T>& D, const T* x, const T* b, T* y, int mode) {
-  HIPCHK(launch_apply<T>(D.a, D.geo, D.tab, x, b, y, mode, D.E, c->stream, true, c->opt_apply_nper));
+  HIPCHK(launch_apply<T>(D.a, D.geo, D.tab, x, b, y, mode, D.E, c->stream, true, c->opt_apply_nper,
+                         c->opt_apply_variant));
 }
 
 // E: the cell-local scratch of the velocity corrections (the level's own, or
@@ -868,10 +870,15 @@ stmg_status stmg_set_option(stmg_ctx* c, int option, int64_t value) {
     case STMG_OPT_NET_CHUNK:
       c->opt_net_chunk = value;
       return STMG_OK;
+    case STMG_OPT_APPLY_LOOP_ORDER:
+      if (value > 2) break;
+      c->opt_apply_variant = (int)value;
+      return STMG_OK;
     default:
-      c->err = "unknown option";
-      return STMG_EINVAL;
+      break;
   }
+  c->err = "unknown option or value";
+  return STMG_EINVAL;
 }
 
 stmg_status stmg_residual(stmg_ctx* c, int level, const double* b, const double* x, double* r) {
@@ -988,7 +995,8 @@ stmg_status stmg_kernel_time(stmg_ctx* c, int which, int level, int reps, double
           HIPCHK(launch_vanka_factored<T>(D.a, D.Asw, D.Bm, D.F, D.Hinv, D.coef, D.r, D.x, (T)c->p.omega, D.E,
                                           c->stream, false));
         else
-          HIPCHK(launch_apply<T>(D.a, D.geo, D.tab, D.x, D.b, D.r, 1, D.E, c->stream, false));
+          HIPCHK(launch_apply<T>(D.a, D.geo, D.tab, D.x, D.b, D.r, 1, D.E, c->stream, false, c->opt_apply_nper,
+                                 c->opt_apply_variant));
       }
       HIPCHK(hipEventRecord(e1, c->stream));
       HIPCHK(hipEventSynchronize(e1));

@@ -19,7 +19,7 @@ lib = ctypes.CDLL(LIB_PATH)
 STATUS = {0: "STMG_OK", -1: "STMG_EINVAL", -2: "STMG_ENOMEM", -3: "STMG_EDEVICE", -4: "STMG_ENOCONV",
           -5: "STMG_ESINGULAR", -6: "STMG_EUNSUPPORTED"}
 FP64, MIXED_FP32 = 0, 1
-OPT_APPLY_SUBINTERVALS, OPT_NET_CHUNK = 1, 2  # stmg_option
+OPT_APPLY_SUBINTERVALS, OPT_NET_CHUNK, OPT_APPLY_LOOP_ORDER = 1, 2, 3  # stmg_option
 VANKA_FACTORED, VANKA_DENSE, VANKA_DECOUPLED, VANKA_AUTO = 0, 1, 2, 3
 LOCAL_EXACT, LOCAL_DIAGONAL = 0, 1
 

@@ -195,15 +195,18 @@ SPLIT_NAMES = [n for n in NAMES if CONFIGS[n]["n_sub"] > 1]
 
 
 @pytest.mark.parametrize("name", SPLIT_NAMES)
-def test_apply_subinterval_split(name):
+@pytest.mark.parametrize("order", [1, 2], ids=["components_outer", "components_inner"])
+def test_apply_subinterval_split(name, order):
     """The operator's cell kernel with every split of the slab among waves:
     one subinterval per wave (the jump term of Eq. (InAlg) read from the
     previous subinterval's nodes) up to all N subintervals walked by one wave
     (the jump term carried in registers), in FP64 (1e-12) and in the FP32
-    V-cycle precision (1e-5 of the largest row; unit roundoff 6e-8)."""
+    V-cycle precision (1e-5 of the largest row; unit roundoff 6e-8), with
+    either loop order of the FP32 3D cell kernel."""
     g64, g32, o = solver(name), solver(name, precision=1), oracle_mg(name)
     rng = np.random.default_rng(12)
     try:
+        g32.set_option(3, order)
         for l, L in enumerate(o.levels):
             x = rng.standard_normal(L.ndofs)
             ref = L.csr() @ x
@@ -216,12 +219,13 @@ def test_apply_subinterval_split(name):
                 g32.set_option(1, nper)
                 g32.apply_vcycle_precision(dev(x), y, level=l)
                 e32 = rel(host(y), ref)
-                announce(f"split {name} level {l} N={N} nper={nper}: fp64 {e64:.2e} fp32 {e32:.2e}")
+                announce(f"split {name} level {l} N={N} nper={nper} order {order}: fp64 {e64:.2e} fp32 {e32:.2e}")
                 assert e64 < 1e-12
                 assert e32 < 1e-5
     finally:
         g64.set_option(1, 0)
         g32.set_option(1, 0)
+        g32.set_option(3, 0)
 
 
 @pytest.mark.parametrize("name", NAMES)

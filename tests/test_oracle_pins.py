@@ -235,3 +235,23 @@ def test_operator_kernel_is_constant_pressure():
         assert np.abs(S.T @ z).max() < 1e-14
     sv = np.linalg.svd(S.toarray(), compute_uv=False)
     assert np.sum(sv < 1e-12 * sv[0]) == L.N * L.nt
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_temporal_eigenvalues_are_the_pade_poles(k):
+    """The temporal decoupling of the cell patches diagonalises
+    diag(c)^{-1} K (c = (tau/2) w); tau times its eigenvalues are those of
+    2 M^{-1} K (M = diag(w)), the poles of the DG(k) stability function,
+    i.e. the roots of the denominator of the (k, k+1) Pade approximant of
+    e^z: Q(z) = sum_j (2k+1-j)! (k+1)! / ((2k+1)! j! (k+1-j)!) (-z)^j.
+    For k = 1 these are 2 +- i sqrt(2): one conjugate pair, no real root."""
+    td = el.temporal_data(k)
+    ev = np.linalg.eigvals(2.0 * np.linalg.solve(td["M"], td["K"]))
+    m, n = k, k + 1
+    q = [factorial(m + n - j) * factorial(n) / (factorial(m + n) * factorial(j) * factorial(n - j)) * (-1) ** j
+         for j in range(n + 1)]
+    roots = np.roots(q[::-1])
+    key = lambda z: (round(z.real, 8), round(z.imag, 8))
+    assert np.allclose(sorted(ev, key=key), sorted(roots, key=key), atol=1e-10 * max(1.0, np.abs(roots).max()))
+    if k == 1:
+        assert np.allclose(sorted(ev, key=key), [2 - 1j * np.sqrt(2), 2 + 1j * np.sqrt(2)], atol=1e-12)
