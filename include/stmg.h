@@ -138,7 +138,7 @@ const char* stmg_last_error(const stmg_ctx* ctx);
  *  STMG_OPT_NET_CHUNK: space-time cells per inference chunk of the learned
  *    correction (0 = default 65536; at most 65536);
  *  STMG_OPT_APPLY_LOOP_ORDER: loop order of the operator's cell kernel on 3D
- *    FP32 levels (0 = automatic: components inner; 1 = components outer, one
+ *    FP32 levels (0 = automatic: components outer; 1 = components outer, one
  *    component's geometry live at a time; 2 = components inner, the pressure
  *    and continuity rows shared by the components).
  * Returns STMG_EINVAL for an unknown option or value. */

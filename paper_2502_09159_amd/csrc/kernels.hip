@@ -802,10 +802,12 @@ static hipError_t apply_impl(const LevelArgs& L, const T* geo, const T* tab, con
   if (nper_req > 0) nchunk = (L.N + std::min(nper_req, L.N) - 1) / std::min(nper_req, L.N);
   const int nper = (int)((L.N + nchunk - 1) / nchunk);
   nchunk = (L.N + nper - 1) / nper;
-  // FP32 3D levels: components inner unless asked otherwise (fewer
-  // instructions); FP64 keeps the components outer (its registers would not fit)
+  // FP32 3D levels: components inner only when asked (variant 2).  It issues
+  // about a quarter fewer instructions but holds 188 registers (2 waves per
+  // SIMD against 4), and measured no faster on Q3 levels and slower on Q2
+  // levels; FP64 always keeps the components outer (its registers would not fit)
   if constexpr (D == 3 && sizeof(T) == 4) {
-    if (variant != 1)
+    if (variant == 2)
       k_apply<T, D, Q, NT, false, true><<<dim3((unsigned)nbx, (unsigned)nchunk), 256, 0, s>>>(L, geo, tab, x, b, y, E,
                                                                                             mode, nper);
     else

@@ -40,7 +40,7 @@ template <typename T>
 // gather = false runs the cell kernel only (E written, y's pressure rows
 // written, velocity rows untouched): for timing.
 // nper > 0 fixes the subintervals one wave walks through (clamped to [1, N]);
-// 0 picks them so that the grid fills the chip.  variant: 0 automatic, 1 the
+// 0 picks them so that the grid fills the chip.  variant: 0 and 1 the
 // components as the outer loop of the cell kernel, 2 as the inner loop (3D
 // FP32 only; elsewhere the outer loop is used).
 hipError_t launch_apply(const LevelArgs& L, const T* geo, const T* tab, const T* x, const T* b, T* y, int mode,
