@@ -210,6 +210,7 @@ def timed_solves(S, b, x, steps, warmup, label, max_it=200):
         info = S.solve(b, x, rtol=1e-8, max_it=max_it, raise_on_noconv=False)
         its.append(info["iterations"])
         disabled.append(info["learned_disabled"])
+    timed_solves.learned_steps = info["learned_steps"]
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / steps
     timed_solves.last_rel = info["rel_residual"]
@@ -397,6 +398,7 @@ def main():
     extra = {}
     if args.variant == "learned":
         extra["learned_switched_off"] = disabled
+        extra["learned_steps_applied"] = timed_solves.learned_steps
     if not args.no_compare and args.variant == "learned":
         # the same FP32 context with the network off, and the network on the
         # network's own element levels only (reading A)

@@ -141,11 +141,16 @@ const char* stmg_last_error(const stmg_ctx* ctx);
  *    FP32 levels (0 = automatic: components outer; 1 = components outer, one
  *    component's geometry live at a time; 2 = components inner, the pressure
  *    and continuity rows shared by the components).
+ *  STMG_OPT_INJECT_NONFINITE: test hook; a value v >= 1 overwrites the
+ *    output of the v-th preconditioner application of every following
+ *    stmg_solve with NaN (as an FP32 overflow in the V-cycle would leave it),
+ *    to exercise the fallback described at stmg_solve; 0 = off.
  * Returns STMG_EINVAL for an unknown option or value. */
 typedef enum {
   STMG_OPT_APPLY_SUBINTERVALS = 1,
   STMG_OPT_NET_CHUNK = 2,
-  STMG_OPT_APPLY_LOOP_ORDER = 3
+  STMG_OPT_APPLY_LOOP_ORDER = 3,
+  STMG_OPT_INJECT_NONFINITE = 4
 } stmg_option;
 stmg_status stmg_set_option(stmg_ctx* ctx, int option, int64_t value);
 
@@ -229,6 +234,10 @@ typedef struct {
   int learned_disabled;    /* 1 if the learned correction was switched off */
   int history_len;
   const double* history;   /* residual estimates, owned by the context */
+  int vcycle_fallbacks;    /* steps whose V-cycle output was not finite and
+                              that were redone with the unpreconditioned
+                              direction */
+  int learned_steps;       /* learned corrections applied before the switch-off */
 } stmg_solve_info;
 
 /* FGMRES (right preconditioned by stmg_vcycle, CGS2, x0 = 0) on the finest
@@ -236,7 +245,11 @@ typedef struct {
  * every STMG_RESTART iterations (fewer if device memory is short).  Returns
  * STMG_ENOCONV if max_it preconditioner applications were not enough (x then
  * holds the last iterate).  info may be NULL.  The returned x has mean-zero
- * pressure in every slice. */
+ * pressure in every slice.  Failure handling: if a V-cycle returns a
+ * non-finite direction (seen in the Gram-Schmidt coefficients that every
+ * step reads back), that step is redone with z_j = the V-cycle's input (no
+ * preconditioning for that step) and counted in info->vcycle_fallbacks; if
+ * that is not finite either, STMG_ESINGULAR. */
 #define STMG_RESTART 64
 stmg_status stmg_solve(stmg_ctx* ctx, const double* b, double* x, double rtol, int max_it,
                        stmg_solve_info* info);
@@ -295,8 +308,9 @@ stmg_status stmg_project_pressure_mean_zero(stmg_ctx* ctx, double* x);
  * weighting of the Vanka patches.  BF16 operands on the matrix cores, FP32
  * accumulation.  The correction c is added with the step alpha = <r, S c> /
  * <S c, S c> that minimises the level's residual 2-norm, so it cannot raise
- * it; if alpha <= 0 the correction is skipped and the network is switched
- * off for the rest of the solve.  A level with another element whose next
+ * it; if that step would remove less than 2% of |r|^2 (alpha <= 0 included)
+ * the correction is skipped and the network is switched off for the rest of
+ * the solve.  A level with another element whose next
  * coarser level has the network's element on the same mesh (e.g. the finest
  * Q3/P2 x DG(1) level above the Q2/P1 x DG(1) level) takes the correction
  * P c_coarse(P^T r) through that level: residual restricted, network

@@ -2417,6 +2417,38 @@ hipError_t launch_dot(const T* a, const T* b, int64_t n, double* partial, double
 template hipError_t launch_dot<double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
 template hipError_t launch_dot<float>(const float*, const float*, int64_t, double*, double*, hipStream_t);
 
+// <r, w>, <w, w>, <r, r> in one pass (FP64 accumulation, fixed order)
+template <typename T>
+__global__ __launch_bounds__(256) void k_dot3(const T* __restrict__ r, const T* __restrict__ w, int64_t n,
+                                              double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double a = (double)r[i], b = (double)w[i];
+    s0 += a * b;
+    s1 += b * b;
+    s2 += a * a;
+  }
+  s0 = block_sum(s0, sh);
+  __syncthreads();
+  s1 = block_sum(s1, sh);
+  __syncthreads();
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = s0;
+    partial[kDotBlocks + blockIdx.x] = s1;
+    partial[2 * kDotBlocks + blockIdx.x] = s2;
+  }
+}
+template <typename T>
+hipError_t launch_dot3(const T* r, const T* w, int64_t n, double* partial, double* out, hipStream_t s) {
+  k_dot3<T><<<kDotBlocks, 256, 0, s>>>(r, w, n, partial);
+  k_dot_final<<<1, 64, 0, s>>>(partial, 3, out);
+  return hipGetLastError();
+}
+template hipError_t launch_dot3<double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
+template hipError_t launch_dot3<float>(const float*, const float*, int64_t, double*, double*, hipStream_t);
+
 // ---- Gram-Schmidt passes of the Arnoldi process (lagged CGS2), templated on
 // a bound NVM of the number of basis vectors (per-thread accumulators; the
 // basis values of one element are kept in registers for NVM <= 32 and read

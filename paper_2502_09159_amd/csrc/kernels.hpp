@@ -160,6 +160,9 @@ hipError_t launch_multidot(const double* V, int64_t ldv, int nv, const double* w
 // partial needs 1024 doubles.
 template <typename T>
 hipError_t launch_dot(const T* a, const T* b, int64_t n, double* partial, double* out, hipStream_t s);
+// out[0..2] = <r, w>, <w, w>, <r, r> in one pass; partial needs 3 * 512 doubles.
+template <typename T>
+hipError_t launch_dot3(const T* r, const T* w, int64_t n, double* partial, double* out, hipStream_t s);
 // One Arnoldi step of classical Gram-Schmidt with one reorthogonalisation,
 // lagged by one step (two passes over the basis).  On entry V_0..V_{j-1} are
 // final; if pending, u holds the previous step's vector after its first

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <mutex>
 #include <type_traits>
@@ -160,6 +161,7 @@ struct stmg_ctx {
   // learned correction
   NetDev net;
   bool net_ready = false, learned_on = false, learned_disabled = false;
+  int learned_steps = 0;  // corrections applied in the current solve
   int learned_reading = 1;  // 1: every level reaching a Q2/P1 x DG(1) level on its mesh; 2: those levels only
   std::vector<void*> lsave;  // per level: copy of x before a correction
   // time marching: right-hand side and Dirichlet values of the current slab
@@ -168,6 +170,7 @@ struct stmg_ctx {
   int opt_apply_nper = 0;      // subintervals per wave of the operator's cell kernel (0: automatic)
   int opt_apply_variant = 0;   // loop order of the operator's cell kernel (0: automatic)
   int64_t opt_net_chunk = 0;   // space-time cells per inference chunk (0: the default)
+  int64_t opt_inject_nonfinite = 0;  // test hook: preconditioner application whose output is made NaN
 };
 
 namespace {
@@ -528,17 +531,8 @@ double norm2(stmg_ctx* c, const T* v, int64_t n);
 
 // After a Vanka sweep: r = b - S x, c = net(r), w = S c and x += alpha c with
 // the residual-minimising alpha = <r, w> / <w, w>, so the level residual
-// cannot grow.  If the direction does not reduce it (alpha <= 0) the
+// cannot grow.  If the direction does not reduce it enough (below) the
 // correction is skipped and switched off for the rest of the solve.
-template <typename T>
-double dot_t(stmg_ctx* c, const T* a, const T* b, int64_t n) {
-  HIPCHK(launch_dot<T>(a, b, n, c->partial, c->dh, c->stream));
-  double h;
-  HIPCHK(hipMemcpyAsync(&h, c->dh, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipStreamSynchronize(c->stream));
-  return h;
-}
-
 // cv = the network correction of the residual r on level l (route 1), or
 // P net(P^T r) through the next level (route 2), with the next level's
 // learned work vectors as temporaries
@@ -560,6 +554,9 @@ void learned_correction_at(stmg_ctx* c, int level, int route, const T* r, T* cv)
   op_prolongate_add<T>(c, H, level, cc, cv);
 }
 
+// Smallest fraction of |r|^2 a learned step must remove to stay switched on.
+constexpr double kLearnedMinGain = 0.02;
+
 // Returns whether it ran: then D.r holds b - S x for the x it leaves (the
 // residual after the update is r - alpha w, so the caller need not apply S again).
 template <typename T>
@@ -572,12 +569,20 @@ bool learned_step(stmg_ctx* c, DevLevel<T>& D, int level, const T* b, T* x) {
   op_apply<T>(c, D, x, b, D.r, 1);
   learned_correction_at<T>(c, level, route, D.r, cv);
   op_apply<T>(c, D, cv, cv, wv, 0);
-  const double rw = dot_t<T>(c, D.r, wv, D.ndofs), ww = dot_t<T>(c, wv, wv, D.ndofs);
-  if (!(rw > 0.0) || !(ww > 0.0) || !std::isfinite(rw / ww)) {
+  double d3[3];  // <r, w>, <w, w>, <r, r>: one reduction, one host synchronisation
+  HIPCHK(launch_dot3<T>(D.r, wv, D.ndofs, c->partial, c->dh, c->stream));
+  HIPCHK(hipMemcpyAsync(d3, c->dh, sizeof(d3), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const double rw = d3[0], ww = d3[1], rr = d3[2];
+  // the step lowers |r|^2 by the fraction rw^2 / (ww rr); below kLearnedMinGain
+  // it is not worth the network's cost, and a step that cannot lower it at
+  // all (rw <= 0, non-finite) would raise the residual
+  if (!(rw > 0.0) || !(ww > 0.0) || !std::isfinite(rw / ww) || !(rw * (rw / ww) >= kLearnedMinGain * rr)) {
     c->learned_disabled = true;
     return true;  // x unchanged: D.r = b - S x
   }
   const T alpha = (T)(rw / ww);
+  ++c->learned_steps;
   HIPCHK(launch_axpy<T>(x, alpha, cv, D.ndofs, c->stream));
   HIPCHK(launch_axpy<T>(D.r, -alpha, wv, D.ndofs, c->stream));
   return true;
@@ -870,6 +875,9 @@ stmg_status stmg_set_option(stmg_ctx* c, int option, int64_t value) {
     case STMG_OPT_NET_CHUNK:
       c->opt_net_chunk = value;
       return STMG_OK;
+    case STMG_OPT_INJECT_NONFINITE:
+      c->opt_inject_nonfinite = value;
+      return STMG_OK;
     case STMG_OPT_APPLY_LOOP_ORDER:
       if (value > 2) break;
       c->opt_apply_variant = (int)value;
@@ -1102,6 +1110,7 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
     const int m = c->cap - 1;
     c->history.clear();
     c->learned_disabled = false;
+    c->learned_steps = 0;
     c->t_smooth.reset();
     c->t_vcyc.reset();
     c->t_op.reset();
@@ -1111,7 +1120,7 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
     HIPCHK(hipEventRecord(e0, s));
     HIPCHK(launch_fill<double>(x, 0.0, n, s));
     double bnorm = std::sqrt(dot(c, b, b, n));
-    int total = 0;
+    int total = 0, applications = 0, fallbacks = 0;
     double rel = 0.0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hv(m + 2), y(m);
     while (true) {
@@ -1137,33 +1146,66 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
       double* uv = c->u;
       double invb = 0.0;
       while (j < m && total < max_it) {
-        if (c->mixed) {
-          // z_j = V(v_j) in FP32 straight into the basis (its FP32 input was
-          // written with v_j); w = S z_j in FP64 on its FP64 copy (an FP64
-          // operator reading FP32 input directly runs slower)
-          float* zj = c->Z32 + (size_t)j * ldv;
-          precondition_f32(c, zj);
-          HIPCHK(launch_cast_f2d(zj, c->zt, n, s));
-          if (c->phase_timing) c->t_op.a(s);
-          op_apply<double>(c, L0, c->zt, c->zt, wv, 0);
-          if (c->phase_timing) c->t_op.b(s);
-        } else {
-          double* zj = c->Z + (size_t)j * ldv;
-          precondition(c, j == 0 ? c->V : uv, zj);
-          if (c->phase_timing) c->t_op.a(s);
-          op_apply<double>(c, L0, zj, zj, wv, 0);
-          if (c->phase_timing) c->t_op.b(s);
-        }
         double* h1 = c->dh;
         double* h2n = c->dh + 256 + 128 * (j & 1);
         const double* h2p = c->dh + 256 + 128 * ((j + 1) & 1);
-        // (mixed: pass 2 also writes the next direction in FP32, the next V-cycle's input)
-        HIPCHK(launch_lcgs2(c->V, ldv, j, j > 0 ? 1 : 0, uv, h2p, invb, wv, n, c->partial, h1, h2n,
-                            c->mixed ? c->H32.L[0].b : nullptr, s));
         std::vector<double> hh(j + 1), h2(j + 2);
-        HIPCHK(hipMemcpyAsync(hh.data(), h1, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(h2.data(), h2n, h2.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        // z_j, w = S z_j and the Gram-Schmidt passes.  identity: z_j is the
+        // V-cycle's input itself (the fallback step after a non-finite V-cycle;
+        // FGMRES admits any z_j)
+        auto arnoldi_step = [&](bool identity) {
+          ++applications;
+          if (c->mixed) {
+            // z_j = V(v_j) in FP32 straight into the basis (its FP32 input was
+            // written with v_j); w = S z_j in FP64 on its FP64 copy (an FP64
+            // operator reading FP32 input directly runs slower)
+            float* zj = c->Z32 + (size_t)j * ldv;
+            if (identity) {
+              // from the FP64 direction (the FP32 copy the V-cycle read was
+              // overwritten by the failed step's second pass)
+              HIPCHK(launch_cast_d2f(j == 0 ? c->V : uv, zj, n, s));
+            } else {
+              precondition_f32(c, zj);
+              if (applications == c->opt_inject_nonfinite)
+                HIPCHK(launch_fill<float>(zj, std::numeric_limits<float>::quiet_NaN(), n, s));
+            }
+            HIPCHK(launch_cast_f2d(zj, c->zt, n, s));
+            if (c->phase_timing) c->t_op.a(s);
+            op_apply<double>(c, L0, c->zt, c->zt, wv, 0);
+            if (c->phase_timing) c->t_op.b(s);
+          } else {
+            double* zj = c->Z + (size_t)j * ldv;
+            const double* vin = j == 0 ? c->V : uv;
+            if (identity) {
+              HIPCHK(hipMemcpyAsync(zj, vin, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            } else {
+              precondition(c, vin, zj);
+              if (applications == c->opt_inject_nonfinite)
+                HIPCHK(launch_fill<double>(zj, std::numeric_limits<double>::quiet_NaN(), n, s));
+            }
+            if (c->phase_timing) c->t_op.a(s);
+            op_apply<double>(c, L0, zj, zj, wv, 0);
+            if (c->phase_timing) c->t_op.b(s);
+          }
+          // (mixed: pass 2 also writes the next direction in FP32, the next V-cycle's input)
+          HIPCHK(launch_lcgs2(c->V, ldv, j, j > 0 ? 1 : 0, uv, h2p, invb, wv, n, c->partial, h1, h2n,
+                              c->mixed ? c->H32.L[0].b : nullptr, s));
+          HIPCHK(hipMemcpyAsync(hh.data(), h1, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+          HIPCHK(hipMemcpyAsync(h2.data(), h2n, h2.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+          HIPCHK(hipStreamSynchronize(s));
+          bool finite = true;
+          for (double v : hh) finite = finite && std::isfinite(v);
+          for (double v : h2) finite = finite && std::isfinite(v);
+          return finite;
+        };
+        if (!arnoldi_step(false)) {
+          // a non-finite preconditioned direction (e.g. an FP32 overflow in
+          // the V-cycle): redo this step with the unpreconditioned direction.
+          // Pass 1 rewrites V_j from the same pending vector, so nothing
+          // else needs undoing.
+          ++fallbacks;
+          if (!arnoldi_step(true)) throw Error(STMG_ESINGULAR, "FGMRES direction is not finite");
+        }
         std::fill(hv.begin(), hv.end(), 0.0);
         double q2 = 0.0;
         for (int i = 0; i <= j; ++i) {
@@ -1223,6 +1265,8 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
         info->t_other_s = info->t_solve_s - tv - info->t_operator_s;
       }
       info->learned_disabled = c->learned_disabled ? 1 : 0;
+      info->vcycle_fallbacks = fallbacks;
+      info->learned_steps = c->learned_steps;
       info->history_len = (int)c->history.size();
       info->history = c->history.data();
     }

@@ -19,7 +19,7 @@ lib = ctypes.CDLL(LIB_PATH)
 STATUS = {0: "STMG_OK", -1: "STMG_EINVAL", -2: "STMG_ENOMEM", -3: "STMG_EDEVICE", -4: "STMG_ENOCONV",
           -5: "STMG_ESINGULAR", -6: "STMG_EUNSUPPORTED"}
 FP64, MIXED_FP32 = 0, 1
-OPT_APPLY_SUBINTERVALS, OPT_NET_CHUNK, OPT_APPLY_LOOP_ORDER = 1, 2, 3  # stmg_option
+OPT_APPLY_SUBINTERVALS, OPT_NET_CHUNK, OPT_APPLY_LOOP_ORDER, OPT_INJECT_NONFINITE = 1, 2, 3, 4  # stmg_option
 VANKA_FACTORED, VANKA_DENSE, VANKA_DECOUPLED, VANKA_AUTO = 0, 1, 2, 3
 LOCAL_EXACT, LOCAL_DIAGONAL = 0, 1
 
@@ -44,7 +44,8 @@ class SolveInfo(ctypes.Structure):
                 ("t_smoother_s", ctypes.c_double), ("t_mg_other_s", ctypes.c_double),
                 ("t_operator_s", ctypes.c_double), ("t_other_s", ctypes.c_double),
                 ("learned_disabled", ctypes.c_int), ("history_len", ctypes.c_int),
-                ("history", ctypes.POINTER(ctypes.c_double))]
+                ("history", ctypes.POINTER(ctypes.c_double)), ("vcycle_fallbacks", ctypes.c_int),
+                ("learned_steps", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -356,4 +357,6 @@ class Solver:
         return dict(iterations=info.iterations, rel_residual=info.rel_residual, t_solve_s=info.t_solve_s,
                     t_smoother_s=info.t_smoother_s, t_mg_other_s=info.t_mg_other_s,
                     t_operator_s=info.t_operator_s, t_other_s=info.t_other_s,
-                    learned_disabled=info.learned_disabled, history=hist, status=code)
+                    learned_disabled=info.learned_disabled, vcycle_fallbacks=info.vcycle_fallbacks,
+                    learned_steps=info.learned_steps,
+                    history=hist, status=code)
