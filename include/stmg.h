@@ -341,8 +341,22 @@ stmg_status stmg_learned_record(stmg_ctx* ctx, const double* b, const double* xs
  * batch order is a permutation drawn from `seed`.  The loss of every step,
  * sum |net - e|^2 / sum |e|^2 over the batch, goes to loss_hist (host, at
  * least epochs * n_pairs * ceil(cells per pair / batch) values). */
-stmg_status stmg_learned_train(stmg_ctx* ctx, const float* r_pairs, const float* e_pairs, int n_pairs,
-                               uint64_t seed, int epochs, int batch, float lr, float* loss_hist);
+stmg_status stmg_learned_train_pairs(stmg_ctx* ctx, const float* r_pairs, const float* e_pairs, int n_pairs,
+                                     uint64_t seed, int epochs, int batch, float lr, float* loss_hist);
+
+/* The whole training of the learned correction in one call, on an FP64
+ * context whose finest level has the network's element (3D, r=1, k=1):
+ * ceil(n_pairs / 2) random forcings (velocity entries U[-1,1) on interior
+ * nodes from a SplitMix64 stream seeded by `seed` and the forcing's index,
+ * pressure rows 0), each solved to 1e-12 by plain multigrid FGMRES, give two
+ * (residual, error) pairs each (stmg_learned_record); then Adam with
+ * learning rate lr, batches of 4096 space-time cells, `epochs` passes
+ * (stmg_learned_train_pairs).  Starts from the loaded weights, or from a
+ * He-normal initialisation drawn from the seed if none are loaded.  The
+ * trained weights (STMG_NET_PARAMS FP32 values) go to weights_out (host) and
+ * stay loaded.  The pairs live in device memory for the call only
+ * (2 n_pairs n_dofs FP32 values). */
+stmg_status stmg_learned_train(stmg_ctx* ctx, int n_pairs, uint64_t seed, int epochs, float lr, float* weights_out);
 
 /* Test hooks on one level, FP64 in and out:
  * u = sum_T R_T^T s_T net(R_T r / s_T) (the correction, no residual check) on

@@ -49,7 +49,11 @@ __device__ void conv_block(const uint16_t* __restrict__ in, const bf16x4* __rest
   for (int it = 0; it < RT / 4; ++it)
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) acc[it][ct] = f32x4{0, 0, 0, 0};
+  // a wave's row tiles rt = wave + 4 it all have rt % 2 == wave % 2, so the
+  // lane's position p, and its neighbour at offset o, do not depend on it
+  const int p = (wave % 2) * 16 + lane % 16;
   for (int o = 0; o < 27; ++o) {
+    const int q = nbr(o, p);
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
       bf16x4 b[CT];
@@ -57,9 +61,7 @@ __device__ void conv_block(const uint16_t* __restrict__ in, const bf16x4* __rest
       for (int ct = 0; ct < CT; ++ct) b[ct] = frag[((o * KB + kb) * CT + ct) * 64 + lane];
 #pragma unroll
       for (int it = 0; it < RT / 4; ++it) {
-        const int rt = wave + 4 * it;
-        const int g = rt / 2, p = (rt % 2) * 16 + lane % 16;
-        const int q = nbr(o, p);
+        const int g = (wave + 4 * it) / 2;
         bf16x4 a = bf16x4{0, 0, 0, 0};
         if (q >= 0) a = *reinterpret_cast<const bf16x4*>(in + (g * 32 + q) * CIP + kb * 16 + 4 * (lane / 16));
 #pragma unroll

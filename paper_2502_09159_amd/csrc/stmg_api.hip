@@ -1440,13 +1440,11 @@ stmg_status stmg_learned_record(stmg_ctx* c, const double* b, const double* xsta
   });
 }
 
-stmg_status stmg_learned_train(stmg_ctx* c, const float* rp, const float* ep, int n_pairs, uint64_t seed, int epochs,
-                               int batch, float lr, float* loss_hist) {
-  if (!c || !rp || !ep || n_pairs < 1 || epochs < 1 || batch < 8 || !(lr > 0) || !c->net_ready)
-    return STMG_EINVAL;
+// Adam over device FP32 pairs (the body of stmg_learned_train_pairs)
+static void train_pairs_impl(stmg_ctx* c, const float* rp, const float* ep, int n_pairs, uint64_t seed, int epochs,
+                             int batch, float lr, float* loss_hist) {
   const LevelArgs& a = c->H64.L[0].a;
-  if (!net_level(a)) { c->err = "training needs a 3D Q2/P1 x DG(1) finest level"; return STMG_EINVAL; }
-  return (stmg_status)guarded(c, [&] {
+  {
     net_alloc(c, batch);
     if (batch > c->net.cap) throw Error(STMG_EINVAL, "batch too large");
     const int64_t nd = c->host[0].ndofs;
@@ -1477,7 +1475,116 @@ stmg_status stmg_learned_train(stmg_ctx* c, const float* rp, const float* ep, in
         if (loss_hist) loss_hist[h++] = red[1] > 0 ? (float)(red[0] / red[1]) : 0.0f;
       }
     }
+  }
+}
+
+stmg_status stmg_learned_train_pairs(stmg_ctx* c, const float* rp, const float* ep, int n_pairs, uint64_t seed,
+                                     int epochs, int batch, float lr, float* loss_hist) {
+  if (!c || !rp || !ep || n_pairs < 1 || epochs < 1 || batch < 8 || !(lr > 0) || !c->net_ready)
+    return STMG_EINVAL;
+  if (!net_level(c->H64.L[0].a)) { c->err = "training needs a 3D Q2/P1 x DG(1) finest level"; return STMG_EINVAL; }
+  return (stmg_status)guarded(c, [&] { train_pairs_impl(c, rp, ep, n_pairs, seed, epochs, batch, lr, loss_hist); });
+}
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): one 64-bit output per
+// counter step; uniform doubles from its top 53 bits.
+namespace {
+struct SplitMix64 {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return (double)(next() >> 11) * (1.0 / 9007199254740992.0); }  // [0, 1)
+};
+}  // namespace
+
+stmg_status stmg_learned_train(stmg_ctx* c, int n_pairs, uint64_t seed, int epochs, float lr, float* weights_out) {
+  if (!c || n_pairs < 2 || epochs < 1 || !(lr > 0) || !weights_out || c->host.size() < 2) return STMG_EINVAL;
+  if (c->mixed) { c->err = "train in an FP64 context"; return STMG_EINVAL; }
+  if (!net_level(c->H64.L[0].a)) { c->err = "training needs a 3D Q2/P1 x DG(1) finest level"; return STMG_EINVAL; }
+  const LevelHost& L = c->host[0];
+  const int64_t nd = L.ndofs;
+  const int n_forc = (n_pairs + 1) / 2, np = 2 * n_forc;
+  constexpr int kBatch = 4096;
+  double *b = nullptr, *xs = nullptr, *r2 = nullptr, *e2 = nullptr;
+  float *rp = nullptr, *ep = nullptr;
+  auto release = [&] {
+    for (void* p : {(void*)b, (void*)xs, (void*)r2, (void*)e2, (void*)rp, (void*)ep})
+      if (p) (void)hipFree(p);
+  };
+  int rc = guarded(c, [&] {
+    if (!c->net_ready) {  // He-normal initialisation drawn from the seed (Box-Muller)
+      SplitMix64 g{seed ^ 0x5DEECE66DULL};
+      std::vector<float> w0(kNetParams);
+      const int cin[3] = {15, 32, 32}, cout[3] = {32, 32, 14};
+      size_t o = 0;
+      for (int l = 0; l < 3; ++l) {
+        const double sd = std::sqrt(2.0 / (cin[l] * 27.0));
+        for (int i = 0; i < cout[l] * cin[l] * 27; ++i) {
+          const double u1 = 1.0 - g.uniform(), u2 = g.uniform();
+          w0[o++] = (float)(sd * std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2));
+        }
+      }
+      net_alloc(c, kBatch);
+      HIPCHK(hipMemcpyAsync(c->net.w, w0.data(), kNetParams * sizeof(float), hipMemcpyHostToDevice, c->stream));
+      HIPCHK(launch_fill<float>(c->net.m, 0.0f, kNetParams, c->stream));
+      HIPCHK(launch_fill<float>(c->net.v, 0.0f, kNetParams, c->stream));
+      HIPCHK(net_pack(c->net, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    HIPCHK(hipMalloc(&b, nd * sizeof(double)));
+    HIPCHK(hipMalloc(&xs, nd * sizeof(double)));
+    HIPCHK(hipMalloc(&r2, 2 * nd * sizeof(double)));
+    HIPCHK(hipMalloc(&e2, 2 * nd * sizeof(double)));
+    HIPCHK(hipMalloc(&rp, (size_t)np * nd * sizeof(float)));
+    HIPCHK(hipMalloc(&ep, (size_t)np * nd * sizeof(float)));
   });
+  if (rc != STMG_OK) { release(); return (stmg_status)rc; }
+  // forcings: velocity entries U[-1, 1) on interior nodes, zero Dirichlet
+  // entries and pressure rows (a consistent right-hand side, Eq. (DefB))
+  std::vector<double> bh(nd);
+  for (int f = 0; f < n_forc && rc == STMG_OK; ++f) {
+    SplitMix64 g{seed * 0x9E3779B97F4A7C15ULL + (uint64_t)f + 1};
+    std::fill(bh.begin(), bh.end(), 0.0);
+    for (int n = 0; n < L.N; ++n)
+      for (int a = 0; a < L.nt; ++a)
+        for (int comp = 0; comp < L.d; ++comp)
+          for (int64_t node = 0; node < L.nodes; ++node) {
+            const int64_t gx = node % L.nn, gy = (node / L.nn) % L.nn, gz = node / ((int64_t)L.nn * L.nn);
+            const bool bnd = gx == 0 || gx == L.nn - 1 || gy == 0 || gy == L.nn - 1 ||
+                             (L.d == 3 && (gz == 0 || gz == L.nn - 1));
+            const double u = 2.0 * g.uniform() - 1.0;
+            if (!bnd) bh[(size_t)(n * L.slab + a * L.Mv + comp * L.nodes + node)] = u;
+          }
+    rc = guarded(c, [&] {
+      HIPCHK(hipMemcpyAsync(b, bh.data(), nd * sizeof(double), hipMemcpyHostToDevice, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+    });
+    if (rc != STMG_OK) break;
+    const bool was_on = c->learned_on;
+    c->learned_on = false;  // the reference solution and the pairs come from plain multigrid
+    stmg_solve_info info;
+    rc = stmg_solve(c, b, xs, 1e-12, 200, &info);
+    if (rc == STMG_OK) rc = stmg_learned_record(c, b, xs, r2, e2);
+    c->learned_on = was_on;
+    if (rc != STMG_OK) break;
+    rc = guarded(c, [&] {
+      HIPCHK(launch_cast_d2f(r2, rp + (size_t)2 * f * nd, 2 * nd, c->stream));
+      HIPCHK(launch_cast_d2f(e2, ep + (size_t)2 * f * nd, 2 * nd, c->stream));
+    });
+  }
+  if (rc == STMG_OK)
+    rc = guarded(c, [&] {
+      train_pairs_impl(c, rp, ep, np, seed, epochs, kBatch, lr, nullptr);
+      HIPCHK(hipMemcpyAsync(weights_out, c->net.w, kNetParams * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(hipStreamSynchronize(c->stream));
+    });
+  (void)hipStreamSynchronize(c->stream);
+  release();
+  return (stmg_status)rc;
 }
 
 stmg_status stmg_learned_correction(stmg_ctx* c, int level, const double* r, double* u) {

@@ -82,7 +82,9 @@ _sig = {
     "stmg_learned_weights": [_P, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t],
     "stmg_learned_enable": [_P, ctypes.c_int],
     "stmg_learned_record": [_P, _P, _P, _P, _P],
-    "stmg_learned_train": [_P, _P, _P, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+    "stmg_learned_train_pairs": [_P, _P, _P, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_float, ctypes.POINTER(ctypes.c_float)],
+    "stmg_learned_train": [_P, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_float,
                            ctypes.POINTER(ctypes.c_float)],
     "stmg_learned_correction": [_P, ctypes.c_int, _P, _P],
     "stmg_learned_gradient": [_P, ctypes.c_int, _P, _P, ctypes.POINTER(ctypes.c_float),
@@ -326,10 +328,19 @@ class Solver:
         cells = N * n ** d
         steps = epochs * n_pairs * ((cells + batch - 1) // batch)
         hist = np.zeros(steps, dtype=np.float32)
-        _check(lib.stmg_learned_train(self.ctx, ctypes.c_void_p(r_pairs.data_ptr()), ctypes.c_void_p(e_pairs.data_ptr()),
-                                      n_pairs, seed, epochs, batch, lr,
-                                      hist.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), self.ctx)
+        _check(lib.stmg_learned_train_pairs(self.ctx, ctypes.c_void_p(r_pairs.data_ptr()),
+                                            ctypes.c_void_p(e_pairs.data_ptr()), n_pairs, seed, epochs, batch, lr,
+                                            hist.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), self.ctx)
         return hist
+
+    def learned_train_seeded(self, n_pairs, seed=0, epochs=20, lr=1e-3):
+        """stmg_learned_train: pairs from random forcings generated and
+        solved inside the library, then Adam; returns the trained weights."""
+        import numpy as np
+        w = np.zeros(NET_PARAMS, dtype=np.float32)
+        _check(lib.stmg_learned_train(self.ctx, n_pairs, seed, epochs, lr,
+                                      w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), self.ctx)
+        return w
 
     def learned_correction(self, r, level=0):
         n = self.ndofs(level)

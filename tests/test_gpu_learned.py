@@ -125,6 +125,40 @@ def test_gradient_matches_oracle(small):
         off += n
 
 
+def test_train_in_one_call():
+    """stmg_learned_train (the call of the boundary that takes n_pairs, seed,
+    epochs and lr): forcings generated and solved inside the library, pairs
+    recorded, Adam; the held-out loss falls below that of the starting
+    weights, and with no weights loaded it starts from its own He-normal
+    initialisation."""
+    from paper_2502_09159_amd import learned, stmg
+    g = stmg.Solver(**CFG)
+    try:
+        w0 = learned.he_init(0)
+        g.learned_load(w0)
+        test_b = [random_rhs(3, 4, 1, 1, 2, s) for s in range(2000, 2004)]
+        rt, et = learned.make_pairs(g, test_b)
+
+        def held_out():
+            return np.mean([g.learned_gradient(rt[i].double().contiguous(), et[i].double().contiguous())[1]
+                            for i in range(rt.shape[0])])
+        loss0 = held_out()
+        w = g.learned_train_seeded(n_pairs=32, seed=5, epochs=4, lr=1e-3)
+        loss1 = held_out()
+        announce(f"one-call training: held-out loss {loss0:.3f} -> {loss1:.3f}")
+        assert np.all(np.isfinite(w)) and not np.array_equal(w, w0)
+        assert np.array_equal(w, g.learned_weights())
+        assert loss1 < loss0
+    finally:
+        g.close()
+    g2 = stmg.Solver(**CFG)
+    try:
+        w2 = g2.learned_train_seeded(n_pairs=4, seed=6, epochs=1, lr=1e-3)
+        assert np.all(np.isfinite(w2)) and np.abs(w2).max() > 0
+    finally:
+        g2.close()
+
+
 @pytest.mark.parametrize("kind", ["nan", "zero"])
 def test_switch_off_on_a_bad_network(kind):
     """A network whose correction cannot reduce the residual (non-finite or
