@@ -268,8 +268,9 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
   const bool cvalid = cid < ncells;
   const bool lvalid = cvalid && qx < Q && qy < Q;
   const int64_t cell = cvalid ? cid : 0;
-  const int cc0 = (int)(cell % L.n), cc1 = (int)((cell / L.n) % L.n),
-            cc2 = D == 3 ? (int)(cell / ((int64_t)L.n * L.n)) : 0;
+  int ccs[3];
+  cell_coords(L, cell, ccs);
+  const int cc0 = ccs[0], cc1 = ccs[1], cc2 = ccs[2];
   const int gxn = cc0 * L.q + qx, gyn = cc1 * L.q + qy;
   const bool fxy = lvalid && gxn > 0 && gxn < L.nn - 1 && gyn > 0 && gyn < L.nn - 1;
   int gnd[ZP];  // node index (< 2^31: checked on the host)
@@ -625,13 +626,19 @@ __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __res
                                                      const T* __restrict__ b, T* __restrict__ out, T omega,
                                                      int lxw) {
   constexpr int q = QQ - 1;
-  const int c = (blockIdx.x << lxw) + (int)(threadIdx.x & ((1 << lxw) - 1));
+  // logical block: consecutive ones share the copies of shared nodes (the two
+  // z-layers of a cache line of a cell, rows straddling two blocks), so they
+  // are kept on one XCD and its L2
+  const int64_t gxy = (int64_t)gridDim.x * gridDim.y;
+  const int64_t lb = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z),
+                               gxy * gridDim.z);
+  const int bx = (int)(lb % gridDim.x), by = (int)((lb / gridDim.x) % gridDim.y);
+  const int c = (bx << lxw) + (int)(threadIdx.x & ((1 << lxw) - 1));
   const int rows = 256 >> lxw, nyb = (L.nn + rows - 1) / rows;
-  const int by = blockIdx.y;
   const int gy = (D == 3 ? by % nyb : by) * rows + (int)(threadIdx.x >> lxw);
   const int gz = D == 3 ? by / nyb : 0;
   if (c >= L.n || gy >= L.nn) return;
-  const int64_t field = blockIdx.z;  // (n nt + a) D + comp
+  const int64_t field = lb / gxy;  // (n nt + a) D + comp
   const int comp = (int)(field % D);
   const int64_t fa = field / D;
   const int64_t row0 = (fa / L.nt) * L.slab + (fa % L.nt) * L.Mv + (int64_t)comp * L.nodes +
@@ -655,7 +662,7 @@ __global__ __launch_bounds__(256) void k_node_gather(LevelArgs L, const T* __res
   constexpr bool CM = KIND == 1;
   constexpr int NLQ = D == 3 ? QQ * QQ * QQ : QQ * QQ;
   const int W = QQ * L.n;
-  const int64_t NE = CM ? (int64_t)(L.Mp / L.C) * NLQ : (D == 3 ? (int64_t)W * W * W : (int64_t)W * W);
+  const int64_t NE = CM ? (int64_t)n_cells(L) * NLQ : (D == 3 ? (int64_t)W * W * W : (int64_t)W * W);
   const T* Ef = E + field * NE;
   const int ny = (gy % q == 0) ? 2 : 1, nz = D == 3 ? ((gz % q == 0) ? 2 : 1) : 1;
   const int dy = gy + gy / q, dz = gz + gz / q;
@@ -942,7 +949,8 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
   T* YP = S + P * 8;
   T* sc = YP + P * 8;
   const int64_t cell = xcd_remap(blockIdx.x, gridDim.x);
-  const int cc[3] = {(int)(cell % L.n), (int)((cell / L.n) % L.n), D == 3 ? (int)(cell / ((int64_t)L.n * L.n)) : 0};
+  int cc[3];
+  cell_coords(L, cell, cc);
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
 
   // ---- A_s^{-1} fragments of this wave's first row tile: issued first, so
@@ -1225,8 +1233,12 @@ hipError_t launch_vanka_factored(const LevelArgs& L, const T* Asw, const T* Bm, 
 // their inverses as nloc complex values per block (re, im), Z_j is formed
 // elementwise while the residual is staged, and F_j = -Dinv_j B^T is formed
 // from B (Ft is not read).
+// FP32 with at most two temporal dofs: at most 96 registers (5 waves per
+// SIMD, as many as the shared memory allows), measured 3% faster than the
+// unconstrained 104 on the Q3 x DG(1) level of 32^3 cells; FP64 and more
+// temporal dofs keep their registers (they would spill).
 template <typename T, int D, int Q, int NT, int NCT, bool DIAG = false>
-__global__ __launch_bounds__(256) void k_vanka_tdec(LevelArgs L, const T* __restrict__ Aw,
+__global__ __launch_bounds__(256, sizeof(T) == 4 && NT <= 2 ? 5 : 1) void k_vanka_tdec(LevelArgs L, const T* __restrict__ Aw,
                                                     const T* __restrict__ Bm, const T* __restrict__ Ft,
                                                     const T* __restrict__ Ht, const T* __restrict__ tw,
                                                     const T* __restrict__ r, T* __restrict__ x, T omega,
@@ -1244,17 +1256,18 @@ __global__ __launch_bounds__(256) void k_vanka_tdec(LevelArgs L, const T* __rest
   const int N = L.N, lgN = N == 1 ? 0 : (N == 2 ? 1 : (N == 4 ? 2 : 3)), DN = D * N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* RZ = reinterpret_cast<T*>(smem_raw);  // R~ in B-operand order, then Z as [j][row][ZS]
-  T* sB = RZ + J * MP * ZS;                // B of this cell, [comp][i][l]
+  // complex vectors of C values per (j, n), as (re, im) pairs in rows of R4
+  // (16-byte aligned): one row is read with a few wide loads
+  T* Sc = RZ + J * MP * ZS;                // Schur right-hand side [j][n][l]
+  T* Pc = Sc + J * 8 * R4;                 // p~ [j][n][l]
+  T* sB = Pc + J * 8 * R4;                 // B of this cell, [comp][i][l]
   T* Rp = sB + C * D * NL;                 // pressure residual as read, [a C + l][n]
-  T* Sr = Rp + NT * C * 8;                 // Schur right-hand side [j C + l][n], real / imaginary
-  T* Si = Sr + J * C * 8;
-  T* Pr = Si + J * C * 8;                  // p~ [j C + l][n], real / imaginary
-  T* Pi = Pr + J * C * 8;
-  T* Sp = Pi + J * C * 8;                  // per wave: partial (B Z_j)^T tiles [wave][j][16][17]
+  T* Sp = Rp + NT * C * 8;                 // per wave: partial (B Z_j)^T tiles [wave][j][16][17]
   const T* tT = tw;                  // T[j][a] (re, im)
   const T* tW = tw + 2 * J * NT;     // Wt[a][j] (re, im)
   const int64_t cell = xcd_remap(blockIdx.x, gridDim.x);
-  const int cc[3] = {(int)(cell % L.n), (int)((cell / L.n) % L.n), D == 3 ? (int)(cell / ((int64_t)L.n * L.n)) : 0};
+  int cc[3];
+  cell_coords(L, cell, cc);
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   auto ridx = [](int j, int part, int ct, int kb, int ln, int slot) {
     return ((((j * 2 + part) * NCT + ct) * NKB + kb) * 64 + ln) * 4 + slot;
@@ -1556,8 +1569,8 @@ __global__ __launch_bounds__(256) void k_vanka_tdec(LevelArgs L, const T* __rest
       pr += tT[(j * NT + a) * 2] * v;
       pi += tT[(j * NT + a) * 2 + 1] * v;
     }
-    Sr[q * N + n] = -sr - pr;
-    Si[q * N + n] = -si - pi;
+    Sc[(j * N + n) * R4 + 2 * l] = -sr - pr;
+    Sc[(j * N + n) * R4 + 2 * l + 1] = -si - pi;
   }
   __syncthreads();
   // ---- p~_j = Hinv_j S_j
@@ -1566,16 +1579,17 @@ __global__ __launch_bounds__(256) void k_vanka_tdec(LevelArgs L, const T* __rest
     const int t = tid + 256 * h;
     if (t < J * C * N) {
       const int pp = t >> lgN, n = t & (N - 1), j = pp / C;
+      T sv[R4];
+      __builtin_memcpy(sv, __builtin_assume_aligned(Sc + (j * N + n) * R4, 16), sizeof(sv));
       T pr = 0, pi = 0;
 #pragma unroll
       for (int l = 0; l < C; ++l) {
-        const T hr = hv[h][2 * l], hi = hv[h][2 * l + 1];
-        const T sr = Sr[(j * C + l) * N + n], si = Si[(j * C + l) * N + n];
-        pr += hr * sr - hi * si;
-        pi += hr * si + hi * sr;
+        const T hr = hv[h][2 * l], hi = hv[h][2 * l + 1], sr = sv[2 * l], si = sv[2 * l + 1];
+        pr = fma(hr, sr, fma(-hi, si, pr));
+        pi = fma(hr, si, fma(hi, sr, pi));
       }
-      Pr[pp * N + n] = pr;
-      Pi[pp * N + n] = pi;
+      Pc[(j * N + n) * R4 + 2 * (pp - j * C)] = pr;
+      Pc[(j * N + n) * R4 + 2 * (pp - j * C) + 1] = pi;
     }
   }
   __syncthreads();
@@ -1587,17 +1601,22 @@ __global__ __launch_bounds__(256) void k_vanka_tdec(LevelArgs L, const T* __rest
       const int q = t >> lgN, n = t & (N - 1), a = q / C, l = q % C;
       T v = 0;
 #pragma unroll
-      for (int j = 0; j < J; ++j)
-        v += tW[(a * J + j) * 2] * Pr[(j * C + l) * N + n] - tW[(a * J + j) * 2 + 1] * Pi[(j * C + l) * N + n];
+      for (int j = 0; j < J; ++j) {
+        const T* pc = Pc + (j * N + n) * R4 + 2 * l;
+        v = fma(tW[(a * J + j) * 2], pc[0], fma(-tW[(a * J + j) * 2 + 1], pc[1], v));
+      }
       x[pidx(L, n, a, cell, l)] = (xzero ? T(0) : xp[e]) + omega * v;
     }
   }
-  // ---- velocity: u~_j = Z_j - F_j p~_j, E[a] = sum_j Re(Wt_aj u~_j) (cell-major)
+  // ---- velocity: u~_j = Z_j - F_j p~_j, E[a] = sum_j Re(Wt_aj u~_j) (cell-major,
+  // e_index: field (n NT + a) D + comp)
+  const int64_t fstride = (int64_t)D * n_cells(L) * NL;  // between fields (n, a) and (n, a + 1)
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int row2 = tid + 256 * k;
     if (row2 >= D * NL) break;
     const int comp = row2 / NL, i = row2 % NL;
+    T* ep = E + e_index(L, comp, cell, i);
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
       if (n >= N) break;
@@ -1605,23 +1624,26 @@ __global__ __launch_bounds__(256) void k_vanka_tdec(LevelArgs L, const T* __rest
 #pragma unroll
       for (int j = 0; j < J; ++j) {
         const T* zz = Z + (j * MP + i) * ZS + comp * N + n;
+        T pv2[R4];
+        __builtin_memcpy(pv2, __builtin_assume_aligned(Pc + (j * N + n) * R4, 16), sizeof(pv2));
         T vr = zz[0], vi = zz[DNP];
 #pragma unroll
         for (int l = 0; l < C; ++l) {
-          const T fr = fv[k][j][2 * l], fi = fv[k][j][2 * l + 1];
-          const T pr = Pr[(j * C + l) * N + n], pi = Pi[(j * C + l) * N + n];
-          vr -= fr * pr - fi * pi;
-          vi -= fr * pi + fi * pr;
+          const T fr = fv[k][j][2 * l], fi = fv[k][j][2 * l + 1], pr = pv2[2 * l], pi = pv2[2 * l + 1];
+          vr = fma(-fr, pr, fma(fi, pi, vr));
+          vi = fma(-fr, pi, fma(-fi, pr, vi));
         }
         ur[j] = vr;
         ui[j] = vi;
       }
 #pragma unroll
       for (int a = 0; a < NT; ++a) {
-        T v = 0;
+        T v = tW[a * J * 2] * ur[0];
+        v = fma(-tW[a * J * 2 + 1], ui[0], v);
 #pragma unroll
-        for (int j = 0; j < J; ++j) v += tW[(a * J + j) * 2] * ur[j] - tW[(a * J + j) * 2 + 1] * ui[j];
-        E[e_index(L, (int64_t)(n * NT + a) * D + comp, cell, i)] = v;
+        for (int j = 1; j < J; ++j) v = fma(tW[(a * J + j) * 2], ur[j], fma(-tW[(a * J + j) * 2 + 1], ui[j], v));
+        *ep = v;
+        ep += fstride;
       }
     }
   }
@@ -1638,8 +1660,9 @@ static hipError_t vanka_tdec_impl(const LevelArgs& L, const T* Aw, const T* Bm, 
   const int64_t ncells = L.Mp / L.C;
   const int DN = D * L.N;
   auto shm = [&](int dnp) {
-    return sizeof(T) * ((size_t)J * MP * (2 * dnp + 1) + (size_t)C * D * NL + (size_t)NT * C * 8 + 4 * (size_t)J * C * 8 +
-                        (size_t)4 * J * 16 * 17);
+    constexpr int R4 = (2 * C + 3) / 4 * 4;
+    return sizeof(T) * ((size_t)J * MP * (2 * dnp + 1) + 2 * (size_t)J * 8 * R4 + (size_t)C * D * NL +
+                        (size_t)NT * C * 8 + (size_t)4 * J * 16 * 17);
   };
   auto run = [&](auto kern, size_t bytes) -> hipError_t {
     if (bytes > 65536) {

@@ -24,8 +24,17 @@ struct LevelArgs {
 //  * smoother (cell-major): cell by cell, local node i = ix + Q (iy + Q iz)
 //    fastest, so that the one-cell-per-work-group smoother writes whole
 //    cache lines (e_index).
+// Spatial cells of a level (Mp < 2^31 is checked when the level is set up).
+__device__ __forceinline__ int n_cells(const LevelArgs& L) { return (int)((unsigned)L.Mp / (unsigned)L.C); }
+// Cell coordinates (x, y, z) of a cell index, x fastest (32-bit arithmetic).
+__device__ __forceinline__ void cell_coords(const LevelArgs& L, int64_t cell, int (&cc)[3]) {
+  const unsigned c = (unsigned)cell, n = (unsigned)L.n, r = c / n;
+  cc[0] = (int)(c - r * n);
+  cc[1] = L.d == 3 ? (int)(r % n) : (int)r;
+  cc[2] = L.d == 3 ? (int)(r / n) : 0;
+}
 __device__ __forceinline__ int64_t e_index(const LevelArgs& L, int64_t field, int64_t cell, int i) {
-  return (field * (L.Mp / L.C) + cell) * L.nloc + i;
+  return (field * n_cells(L) + cell) * L.nloc + i;
 }
 
 // Small per-level tables, in the arithmetic type T, packed as

@@ -176,6 +176,9 @@ struct stmg_ctx {
 namespace {
 
 LevelArgs level_args(const LevelHost& L) {
+  // the kernels index cells, nodes and pressure dofs of one field in 32 bits
+  if (L.nodes >= (int64_t(1) << 31) || L.Mp >= (int64_t(1) << 31))
+    throw Error(STMG_EUNSUPPORTED, "level with 2^31 or more nodes or pressure dofs per field");
   LevelArgs a;
   a.d = L.d; a.n = L.n; a.q = L.q; a.Q = L.Q; a.nn = L.nn; a.nt = L.nt; a.C = L.C; a.N = L.N; a.nloc = L.nloc;
   a.nodes = L.nodes; a.Mv = L.Mv; a.Mp = L.Mp; a.slab = L.slab;
