@@ -17,9 +17,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int G = 8;  // samples per work group (256 threads, 4 waves)
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-  return (uint16_t)(u >> 16);
+  return __builtin_bit_cast(uint16_t, (__bf16)f);  // round to nearest even (one instruction on gfx950)
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
@@ -39,7 +37,8 @@ constexpr int OFF_W1 = 0, OFF_W2 = 32 * 15 * 27, OFF_W3 = OFF_W2 + 32 * 32 * 27;
 // One convolution over the G samples in LDS: out[g][p][co] = sum_o sum_ci in[g][nbr(o,p)][ci] W.
 // frag: B operands, ((o KB + kb) CT + ct) 64 + lane, 4 BF16 each.
 // MODE 0: ReLU -> BF16 out (LDS);  1: FP32 out (LDS);  2: x relu'(act) -> BF16 out
-template <int CIP, int COP, int MODE, int GS = G>
+// RSI / RSO: row strides (elements) of in and out (act has out's layout)
+template <int CIP, int COP, int MODE, int GS = G, int RSI = CIP, int RSO = COP>
 __device__ void conv_block(const uint16_t* __restrict__ in, const bf16x4* __restrict__ frag, void* out,
                            const uint16_t* __restrict__ act) {
   constexpr int KB = CIP / 16, CT = COP / 16, RT = GS * 2;
@@ -52,21 +51,33 @@ __device__ void conv_block(const uint16_t* __restrict__ in, const bf16x4* __rest
   // a wave's row tiles rt = wave + 4 it all have rt % 2 == wave % 2, so the
   // lane's position p, and its neighbour at offset o, do not depend on it
   const int p = (wave % 2) * 16 + lane % 16;
+  // The offsets are unrolled, so that the loads of later offsets are issued
+  // ahead of the matrix products of earlier ones.  A missing neighbour reads
+  // row 27 of the sample, a padding row: every activation and gradient array
+  // keeps rows 27..31 at zero (the network inputs and the loss gradient are
+  // written so, and conv_block writes zeros there).  Bit o of nb is set when
+  // position p has a neighbour at offset o.
+  int nb = 0;
+#pragma unroll
+  for (int o = 0; o < 27; ++o) nb |= (nbr(o, p) >= 0 ? 1 : 0) << o;
+#pragma unroll
   for (int o = 0; o < 27; ++o) {
-    const int q = nbr(o, p);
+    const int shift = (o % 3 - 1) + 3 * ((o / 3) % 3 - 1) + 9 * (o / 9 - 1);
+    const int q = (nb >> o) & 1 ? p + shift : 27;
+    const uint16_t* row = in + q * RSI + 4 * (lane / 16);
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
-      bf16x4 b[CT];
+      bf16x4 b[CT], a[RT / 4];
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) b[ct] = frag[((o * KB + kb) * CT + ct) * 64 + lane];
 #pragma unroll
-      for (int it = 0; it < RT / 4; ++it) {
-        const int g = (wave + 4 * it) / 2;
-        bf16x4 a = bf16x4{0, 0, 0, 0};
-        if (q >= 0) a = *reinterpret_cast<const bf16x4*>(in + (g * 32 + q) * CIP + kb * 16 + 4 * (lane / 16));
+      for (int it = 0; it < RT / 4; ++it)
+        a[it] = *reinterpret_cast<const bf16x4*>(row + ((wave + 4 * it) / 2) * 32 * RSI + kb * 16);
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[it][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[ct], acc[it][ct], 0, 0, 0);
-      }
+      for (int it = 0; it < RT / 4; ++it)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+          acc[it][ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[it], b[ct], acc[it][ct], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -80,12 +91,12 @@ __device__ void conv_block(const uint16_t* __restrict__ in, const bf16x4* __rest
         const int p = row % 32, co = ct * 16 + lane % 16;
         float val = p < 27 ? acc[it][ct][v] : 0.0f;
         if (MODE == 0) {
-          static_cast<uint16_t*>(out)[row * COP + co] = to_bf16(fmaxf(val, 0.0f));
+          static_cast<uint16_t*>(out)[row * RSO + co] = to_bf16(fmaxf(val, 0.0f));
         } else if (MODE == 1) {
-          static_cast<float*>(out)[row * COP + co] = val;
+          static_cast<float*>(out)[row * RSO + co] = val;
         } else {
-          float d = from_bf16(act[row * COP + co]) > 0.0f ? val : 0.0f;
-          static_cast<uint16_t*>(out)[row * COP + co] = to_bf16(d);
+          float d = from_bf16(act[row * RSO + co]) > 0.0f ? val : 0.0f;
+          static_cast<uint16_t*>(out)[row * RSO + co] = to_bf16(d);
         }
       }
   }
@@ -95,23 +106,32 @@ __device__ void conv_block(const uint16_t* __restrict__ in, const bf16x4* __rest
 // x: [s][32][16] BF16 -> h1, h2 [s][32][32] BF16 (optional) -> y [s][32][16] FP32
 // Inference only (no activations kept): GI samples per work group, with two
 // LDS regions reused layer by layer (A: h1, then y; B: x, then h2), so that
-// twice the samples share each weight fragment a wave reads.
-constexpr int GI = 16;
-__global__ __launch_bounds__(256) void k_net_infer(const uint16_t* __restrict__ x, const bf16x4* __restrict__ fw,
+// twice the samples share each weight fragment a wave reads.  BF16 rows are
+// padded by 4 elements (8 bytes): the 16 positions a wave reads at once then
+// start in 16 different LDS banks (unpadded 32- and 64-byte rows put 4 or 8
+// of them on the same bank).
+constexpr int GI = 16, RS16 = 16 + 4, RS32 = 32 + 4;
+__global__ __launch_bounds__(256, 2) void k_net_infer(const uint16_t* __restrict__ x, const bf16x4* __restrict__ fw,
                                                    float* __restrict__ y, int64_t count) {
-  static_assert(GI * 32 * 16 * sizeof(float) == GI * 32 * 32 * sizeof(uint16_t), "region A holds h1, then y");
-  __shared__ __align__(16) uint16_t sA[GI * 32 * 32];
-  __shared__ __align__(16) uint16_t sB[GI * 32 * 32];
+  static_assert(GI * 32 * 16 * sizeof(float) <= GI * 32 * RS32 * sizeof(uint16_t), "region A holds h1, then y");
+  __shared__ __align__(16) uint16_t sA[GI * 32 * RS32];
+  __shared__ __align__(16) uint16_t sB[GI * 32 * RS32];
   const int64_t s0 = (int64_t)blockIdx.x * GI;
   const int ns = (int)min<int64_t>(GI, count - s0);
-  for (int t = threadIdx.x; t < GI * 32 * 16; t += blockDim.x) sB[t] = (t / 512) < ns ? x[s0 * 512 + t] : 0;
+  // x rows of 16 BF16 as 4 chunks of 8 bytes
+  for (int t = threadIdx.x; t < GI * 32 * 4; t += blockDim.x) {
+    const int row = t / 4, c4 = t % 4;
+    const unsigned long long v =
+        (row / 32) < ns ? reinterpret_cast<const unsigned long long*>(x + s0 * 512)[t] : 0ull;
+    *reinterpret_cast<unsigned long long*>(sB + row * RS16 + 4 * c4) = v;
+  }
   __syncthreads();
-  conv_block<16, 32, 0, GI>(sB, fw, sA, nullptr);
+  conv_block<16, 32, 0, GI, RS16, RS32>(sB, fw, sA, nullptr);
   __syncthreads();
-  conv_block<32, 32, 0, GI>(sA, fw + F1 / 4, sB, nullptr);
+  conv_block<32, 32, 0, GI, RS32, RS32>(sA, fw + F1 / 4, sB, nullptr);
   __syncthreads();
   float* sy = reinterpret_cast<float*>(sA);
-  conv_block<32, 16, 1, GI>(sB, fw + (F1 + F2) / 4, sy, nullptr);
+  conv_block<32, 16, 1, GI, RS32, 16>(sB, fw + (F1 + F2) / 4, sy, nullptr);
   __syncthreads();
   for (int t = threadIdx.x; t < ns * 512; t += blockDim.x) y[s0 * 512 + t] = sy[t];
 }
