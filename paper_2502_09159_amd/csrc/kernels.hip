@@ -944,12 +944,16 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // Z rows are padded by one value (ZS): consecutive rows fall on consecutive banks
   constexpr int ZS = DNP + 1;
+  constexpr int P4 = (P + 3) / 4 * 4;      // row length of F and H^{-1} (vanka_row_pad), and of YP
+  // the Schur sums over (comp, node) are split KS ways so that P N KS items fill the work group
+  constexpr int KS = P * 8 >= 256 ? 1 : (P * 8 >= 128 ? 2 : 4);
   T* RZ = reinterpret_cast<T*>(smem_raw);  // R (B-operand order), then Z (row-major MP x ZS)
-  T* sB = RZ + MP * ZS;                    // B of this cell, [comp][i][l] (l fastest: no bank conflicts)
+  T* YP = RZ + MP * ZS;                    // y_p as [n][q] (rows of P4, 16-byte aligned)
+  T* sB = YP + 8 * P4;                     // B of this cell, [comp][i][l] (l fastest: no bank conflicts)
   T* Rp = sB + C * D * NL;                 // pressure residual [q][n]
-  T* S = Rp + P * 8;
-  T* YP = S + P * 8;
-  T* sc = YP + P * 8;
+  T* S = Rp + P * 8;                       // Schur right-hand side [q][n]
+  T* Sp = S + P * 8;                       // its KS partial sums [k][q][n]
+  T* sc = Sp + KS * P * 8;
   const int64_t cell = xcd_remap(blockIdx.x, gridDim.x);
   int cc[3];
   cell_coords(L, cell, cc);
@@ -1007,12 +1011,16 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
     }
     const T cv = coef[min(tid, NT - 1)];
     load_tile(min(wave, NKB - 1), fa[0]);
-    // padding entries
-    for (int idx = tid; idx < MP * DNP; idx += 256) {
-      const int r4 = idx & 3, u = idx >> 2, l64 = u & 63;
-      const int K = ((u >> 6) % NKB) * 16 + 4 * (l64 >> 4) + r4;
-      const int col = (u >> 6) / NKB * 16 + (l64 & 15);
-      if (K >= M || col >= DN) RZ[idx] = T(0);
+    // padding entries (K >= M or column >= d N): only the last row tile and
+    // the last column tile hold any; one entry of a tile per thread
+    {
+      const int l64 = tid >> 2, sl = tid & 3;
+      for (int tile = 0; tile < NCT * NKB; ++tile) {
+        const int kb = tile % NKB, ct = tile / NKB;
+        if (!((kb == NKB - 1 && M < MP) || (ct == NCT - 1 && DN < DNP))) continue;  // (uniform)
+        const int K = kb * 16 + 4 * (l64 >> 4) + sl, col = ct * 16 + (l64 & 15);
+        if (K >= M || col >= DN) RZ[tile * 256 + tid] = T(0);
+      }
     }
 #pragma unroll
     for (int e = 0; e < IMAX; ++e) {
@@ -1087,7 +1095,6 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
   // fragments are dead) so that their latency overlaps the Schur complement
   constexpr int RPT = (D * M + 255) / 256;  // velocity rows per thread
   constexpr int HPT = (P * 8 + 255) / 256;  // (pp, n) items per thread, N <= 8
-  constexpr int P4 = (P + 3) / 4 * 4;  // row length of F and H^{-1} (vanka_row_pad)
   const T* Fc = F + cell * (int64_t)D * M * P4;
   const T* H = Hinv + cell * (int64_t)P * P4;
   T fv[RPT][P], hv[HPT][P], xp[HPT];
@@ -1116,15 +1123,28 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
   __syncthreads();
   const T* Z = RZ;
 
-  // ---- pressure Schur complement: S = -c_a B Z - r_p, y_p = H^{-1} S
-  for (int t = tid; t < P * N; t += 256) {
-    const int q = t >> lgN, n = t & (N - 1), a = q / C, l = q % C;
+  // ---- pressure Schur complement: S = -c_a B Z - r_p, y_p = H^{-1} S.  The
+  // sums over the local nodes are split KS ways (item t = (q n) KS + k), the
+  // partial sums added in a fixed order after a barrier.
+  constexpr int ISPL = (NL + KS - 1) / KS;
+  for (int t = tid; t < P * N * KS; t += 256) {
+    const int k = t % KS, it = t / KS, q = it >> lgN, n = it & (N - 1), a = q / C, l = q % C;
     T s = 0;
 #pragma unroll
     for (int comp = 0; comp < D; ++comp)
-#pragma unroll 16
-      for (int i = 0; i < NL; ++i) s += sB[(comp * NL + i) * C + l] * Z[(a * NL + i) * ZS + comp * N + n];
-    S[q * N + n] = -sc[a] * s - Rp[q * N + n];
+#pragma unroll
+      for (int ii = 0; ii < ISPL; ++ii) {
+        const int i = k * ISPL + ii;
+        if (i < NL) s += sB[(comp * NL + i) * C + l] * Z[(a * NL + i) * ZS + comp * N + n];
+      }
+    Sp[k * P * 8 + it] = s;
+  }
+  __syncthreads();
+  for (int t = tid; t < P * N; t += 256) {
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) s += Sp[k * P * 8 + t];
+    S[t] = -sc[(t >> lgN) / C] * s - Rp[t];
   }
   __syncthreads();
 #pragma unroll
@@ -1135,27 +1155,32 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
       T s = 0;
 #pragma unroll
       for (int q = 0; q < P; ++q) s += hv[j][q] * S[q * N + n];
-      YP[pp * N + n] = s;
+      YP[n * P4 + pp] = s;
       x[pidx(L, n, pp / C, cell, pp % C)] = (xzero ? T(0) : xp[j]) + omega * s;  // xzero: x starts at 0
     }
   }
   __syncthreads();
 
   // ---- velocity: y = z - F y_p into the cell-local scratch E (cell-major:
-  // the work group writes whole cache lines)
+  // the work group writes whole cache lines; e_index, field (n NT + a) D + comp)
+  const int64_t nstride = (int64_t)NT * D * n_cells(L) * NL;  // between fields (n, a) and (n + 1, a)
 #pragma unroll
   for (int j = 0; j < RPT; ++j) {
     const int row2 = tid + 256 * j;
     if (row2 >= D * M) break;
     const int comp = row2 / M, row = row2 % M, a = row / NL, i = row % NL;
     const T(&f)[P] = fv[j];
+    T* ep = E + e_index(L, a * D + comp, cell, i);
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
       if (n >= N) break;
+      T yp[P4];
+      __builtin_memcpy(yp, __builtin_assume_aligned(YP + n * P4, 16), sizeof(yp));
       T v = Z[row * ZS + comp * N + n];
 #pragma unroll
-      for (int q = 0; q < P; ++q) v -= f[q] * YP[q * N + n];
-      E[e_index(L, (int64_t)(n * NT + a) * D + comp, cell, i)] = v;
+      for (int q = 0; q < P; ++q) v = fma(-f[q], yp[q], v);
+      *ep = v;
+      ep += nstride;
     }
   }
 }
@@ -1176,7 +1201,10 @@ static hipError_t vanka_fact_impl(const LevelArgs& L, const T* Asw, const T* Bm,
   if (MP / 16 > 16) return hipErrorInvalidValue;  // at most 4 row tiles per wave
   const int64_t ncells = L.Mp / L.C;
   const int DN = D * L.N;
-  auto shm = [&](int dnp) { return sizeof(T) * ((size_t)MP * (dnp + 1) + (size_t)C * D * NL + 3 * (size_t)P * 8 + 8); };
+  constexpr int P4 = (P + 3) / 4 * 4, KS = P * 8 >= 256 ? 1 : (P * 8 >= 128 ? 2 : 4);
+  auto shm = [&](int dnp) {
+    return sizeof(T) * ((size_t)MP * (dnp + 1) + 8 * (size_t)P4 + (size_t)C * D * NL + (2 + KS) * (size_t)P * 8 + 8);
+  };
   auto run = [&](auto kern, size_t bytes) -> hipError_t {
     if (bytes > 65536) {  // beyond the default dynamic LDS limit
       hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
