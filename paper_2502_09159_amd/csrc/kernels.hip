@@ -198,6 +198,28 @@ __device__ __forceinline__ void pencil(const T (&v)[ZP], T (&o)[ZP], int mat, co
 
 }  // namespace
 
+// The pressure modes of degree R in 3D as products of shifted Legendre
+// factors P_a(x) P_b(y) P_c(z), in the library's mode order (total degree
+// 0..R, then the x exponent largest first, then the y exponent): for each
+// mode, the index of (a, b) among the pairs with a + b <= R (by a + b, then a
+// largest first) and c.
+struct PMode {
+  int pair, c;
+};
+template <int R>
+struct PModes {
+  PMode m[(R + 1) * (R + 2) * (R + 3) / 6];
+};
+template <int R>
+__host__ __device__ constexpr PModes<R> pmodes() {
+  PModes<R> t{};
+  int idx = 0;
+  for (int d = 0; d <= R; ++d)
+    for (int a = d; a >= 0; --a)
+      for (int b = d - a; b >= 0; --b) t.m[idx++] = PMode{(a + b) * (a + b + 1) / 2 + b, d - a - b};
+  return t;
+}
+
 // FULL: every column of the operator, Dirichlet ones included (x is read at
 // every node), and for the first subinterval the jump term takes the end
 // value v0 of the previous slab (d x nodes, or none): y = b - S_full x - C^1 v0
@@ -218,7 +240,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
   constexpr int C = D == 3 ? (Q - 1) * Q * (Q + 1) / 6 : (Q - 1) * Q / 2;
   __shared__ __align__(16) T sCX[64];
   __shared__ __align__(16) T sCY[64];
-  __shared__ T sPsi[16 * ZP * C];
+  __shared__ T sPsi[D == 3 ? 1 : 16 * ZP * C];  // 2D only
   __shared__ int sSrc[2][4][4];
   const int tid = threadIdx.x, lane16 = tid & 15, qx = lane16 & 3, qy = lane16 >> 2;
   const T* tS = tab;
@@ -252,7 +274,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
     sCY[tid] = mat_el(mat, i, sSrc[1][m][i]);
   }
   // sPsi[(z C + l) 16 + lane16]: the lanes of a row read consecutive words (no bank conflicts)
-  for (int t = tid; t < 16 * ZP * C; t += blockDim.x) {
+  for (int t = tid; t < (D == 3 ? 0 : 16 * ZP * C); t += blockDim.x) {
     const int ll = t % 16, l = (t / 16) % C, z = t / (16 * C), px = ll & 3, py = ll >> 2;
     sPsi[t] = (px < Q && py < Q) ? tpsi[(px + Q * py + Q * Q * z) * C + l] : T(0);
   }
@@ -288,6 +310,84 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
   const int64_t NE = D == 3 ? (int64_t)W * W * W : (int64_t)W * W;
   T* Ec = E + (cc0 * Q + qx) + (int64_t)W * (cc1 * Q + qy) + (D == 3 ? (int64_t)W * W * cc2 * Q : 0);
   const int po = lane16;  // this lane's column of the psi table
+  // 3D: the pressure and continuity rows use the factors of the modes
+  // (pmodes): pxy[pair] is this lane's (x, y) factor at its Gauss point (0 on
+  // padded lanes), pz[c][z] the z factor at Gauss point z, both read from the
+  // psi table at the modes (a, b, 0) and (0, 0, c) (P_0 = 1).  A pressure value
+  // then costs C + (R + 1) ZP multiply-adds per lane instead of C ZP.
+  constexpr int R = Q - 2, NPAIR = (R + 1) * (R + 2) / 2;
+  constexpr PModes<R> PM = pmodes<R>();
+  T pxy[D == 3 ? NPAIR : 1], pz[D == 3 ? R + 1 : 1][ZP];
+  if constexpr (D == 3) {
+    const bool inq = qx < Q && qy < Q;
+    const int pxyi = min(qx, Q - 1) + Q * min(qy, Q - 1);
+#pragma unroll
+    for (int l = 0; l < C; ++l) {
+      const PMode m = PM.m[l];
+      if (m.c == 0) pxy[m.pair] = inq ? tpsi[pxyi * C + l] : T(0);
+      if (m.pair == 0)
+#pragma unroll
+        for (int z = 0; z < ZP; ++z) pz[m.c][z] = tpsi[(Q * Q * z) * C + l];
+    }
+  }
+  // pressure of the C modes pl at this lane's Gauss points
+  auto pressure_at = [&](const T (&pl)[C], T (&pres)[ZP], int pr) {
+    if constexpr (D == 3) {
+      T A[R + 1];
+#pragma unroll
+      for (int c = 0; c <= R; ++c) A[c] = 0;
+#pragma unroll
+      for (int l = 0; l < C; ++l) {
+        const PMode m = PM.m[l];
+        A[m.c] += pl[l] * pxy[m.pair];
+      }
+#pragma unroll
+      for (int z = 0; z < ZP; ++z) {
+        T v = 0;
+#pragma unroll
+        for (int c = 0; c <= R; ++c) v += pz[c][z] * A[c];
+        pres[z] = v;
+      }
+    } else {
+#pragma unroll
+      for (int z = 0; z < ZP; ++z) {
+        T v = 0;
+#pragma unroll
+        for (int l = 0; l < C; ++l) v += sPsi[pr + (z * C + l) * 16] * pl[l];
+        pres[z] = v;
+      }
+    }
+  };
+  // continuity rows: sum over the cell's Gauss points of psi_l dv, mode l in lane l
+  auto continuity = [&](const T (&dv)[ZP], int pr) -> T {
+    T mine = 0;
+    if constexpr (D == 3) {
+      T B[R + 1];
+#pragma unroll
+      for (int c = 0; c <= R; ++c) {
+        T v = 0;
+#pragma unroll
+        for (int z = 0; z < ZP; ++z) v += pz[c][z] * dv[z];
+        B[c] = v;
+      }
+#pragma unroll
+      for (int l = 0; l < C; ++l) {
+        const PMode m = PM.m[l];
+        const T v = row_sum16(pxy[m.pair] * B[m.c]);
+        if (lane16 == l) mine = v;
+      }
+    } else {
+#pragma unroll
+      for (int l = 0; l < C; ++l) {
+        T v = 0;
+#pragma unroll
+        for (int z = 0; z < ZP; ++z) v += sPsi[pr + (z * C + l) * 16] * dv[z];
+        v = row_sum16(v);
+        if (lane16 == l) mine = v;
+      }
+    }
+    return mine;
+  };
 
   // nodal values of (n, temporal dof bb, comp) interpolated to the Gauss
   // points (n = -1: the previous slab's end value v0, FULL only)
@@ -361,14 +461,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
             const T v = ps[l];
             pl[l] = cvalid ? v : T(0);
           }
-          const int pr = opaque_v(po);
-#pragma unroll
-          for (int z = 0; z < ZP; ++z) {
-            T s = 0;
-#pragma unroll
-            for (int l = 0; l < C; ++l) s += sPsi[pr + (z * C + l) * 16] * pl[l];
-            pres[z] = s;
-          }
+          pressure_at(pl, pres, opaque_v(po));
         }
         T dvs[ZP];
 #pragma unroll
@@ -430,16 +523,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
         }
         // continuity rows of dof a, all components at once
         {
-          const int pr = opaque_v(po);
-          T mine = 0;
-#pragma unroll
-          for (int l = 0; l < C; ++l) {
-            T s = 0;
-#pragma unroll
-            for (int z = 0; z < ZP; ++z) s += sPsi[pr + (z * C + l) * 16] * dvs[z];
-            s = row_sum16(s);
-            if (lane16 == l) mine = s;
-          }
+          const T mine = continuity(dvs, opaque_v(po));
           if (cvalid && lane16 < C) y[prow + lane16] = mode ? prev_in - mine : mine;
         }
 #pragma unroll
@@ -504,14 +588,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
             const T v = ps[l];
             pl[l] = cvalid ? v : T(0);
           }
-          const int pr = opaque_v(po);
-#pragma unroll
-          for (int z = 0; z < ZP; ++z) {
-            T s = 0;
-#pragma unroll
-            for (int l = 0; l < C; ++l) s += sPsi[pr + (z * C + l) * 16] * pl[l];
-            pres[z] = s;
-          }
+          pressure_at(pl, pres, opaque_v(po));
         }
         T Zq[ZP];
 #pragma unroll
@@ -579,16 +656,7 @@ __global__ __launch_bounds__(256) void k_apply(LevelArgs L, const T* __restrict_
         // continuity rows of dof a: y_p[l] (+)= -c_a sum_q psi_l(q) JxW d_comp u_a(q),
         // accumulated over the components in a fixed order
         {
-          const int pr = opaque_v(po);
-          T mine = 0;
-#pragma unroll
-          for (int l = 0; l < C; ++l) {
-            T s = 0;
-#pragma unroll
-            for (int z = 0; z < ZP; ++z) s += sPsi[pr + (z * C + l) * 16] * dv[z];
-            s = row_sum16(s);
-            if (lane16 == l) mine = s;
-          }
+          const T mine = continuity(dv, opaque_v(po));
           if (cvalid && lane16 < C) {
             const T prev = comp > 0 || mode ? prev_in : T(0);
             y[prow + lane16] = mode ? prev - mine : prev + mine;
