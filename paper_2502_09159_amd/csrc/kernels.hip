@@ -170,6 +170,84 @@ __device__ __forceinline__ int opaque_s(int v) {
   return v;
 }
 
+// FP32, all Q values of a pencil along x (DIR 0) or y (DIR 1) in one block:
+// Q multiplies, then the three permuted FMAs of every value.  The first
+// permuted read of an input comes Q instructions after the block starts (at
+// least the two wait states a vector write needs before a permuted read of
+// the same register), so only the results need the wait at the end.
+template <int DIR, int ZP>
+__device__ __forceinline__ void pencil_contract_f32(const float (&v)[ZP], float (&o)[ZP], const float (&c)[4]) {
+  if constexpr (ZP == 4) {
+    float r0, r1, r2, r3;
+    if constexpr (DIR == 0)
+      asm("v_mul_f32 %0, %8, %4\n\tv_mul_f32 %1, %8, %5\n\tv_mul_f32 %2, %8, %6\n\tv_mul_f32 %3, %8, %7\n\t"
+          "v_fmac_f32_dpp %0, %4, %9 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %1, %5, %9 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %2, %6, %9 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %3, %7, %9 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %0, %4, %10 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %1, %5, %10 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %2, %6, %10 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %3, %7, %10 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %0, %4, %11 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %1, %5, %11 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %2, %6, %11 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %3, %7, %11 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "s_nop 1"
+          : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
+          : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    else
+      asm("v_mul_f32 %0, %8, %4\n\tv_mul_f32 %1, %8, %5\n\tv_mul_f32 %2, %8, %6\n\tv_mul_f32 %3, %8, %7\n\t"
+          "v_fmac_f32_dpp %0, %4, %9 row_ror:12 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %1, %5, %9 row_ror:12 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %2, %6, %9 row_ror:12 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %3, %7, %9 row_ror:12 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %0, %4, %10 row_ror:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %1, %5, %10 row_ror:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %2, %6, %10 row_ror:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %3, %7, %10 row_ror:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %0, %4, %11 row_ror:4 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %1, %5, %11 row_ror:4 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %2, %6, %11 row_ror:4 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %3, %7, %11 row_ror:4 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "s_nop 1"
+          : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
+          : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    o[0] = r0; o[1] = r1; o[2] = r2; o[3] = r3;
+  } else {
+    float r0, r1, r2;
+    if constexpr (DIR == 0)
+      asm("v_mul_f32 %0, %6, %3\n\tv_mul_f32 %1, %6, %4\n\tv_mul_f32 %2, %6, %5\n\t"
+          "v_fmac_f32_dpp %0, %3, %7 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %1, %4, %7 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %2, %5, %7 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %0, %3, %8 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %1, %4, %8 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %2, %5, %8 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %0, %3, %9 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %1, %4, %9 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %2, %5, %9 quad_perm:[3,0,1,2] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "s_nop 1"
+          : "=&v"(r0), "=&v"(r1), "=&v"(r2)
+          : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    else
+      asm("v_mul_f32 %0, %6, %3\n\tv_mul_f32 %1, %6, %4\n\tv_mul_f32 %2, %6, %5\n\t"
+          "v_fmac_f32_dpp %0, %3, %7 row_ror:12 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %1, %4, %7 row_ror:12 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %2, %5, %7 row_ror:12 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %0, %3, %8 row_ror:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %1, %4, %8 row_ror:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %2, %5, %8 row_ror:8 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %0, %3, %9 row_ror:4 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %1, %4, %9 row_ror:4 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "v_fmac_f32_dpp %2, %5, %9 row_ror:4 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+          "s_nop 1"
+          : "=&v"(r0), "=&v"(r1), "=&v"(r2)
+          : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]));
+    o[0] = r0; o[1] = r1; o[2] = r2;
+  }
+}
+
 // Pencil contraction with 1D matrix `mat` (0: S, 1: Dg, 2: S^T, 3: Dg^T) along
 // direction DIR of a cell.  x / y: per-lane coefficients cxy[co + m] in LDS
 // (co = mat * 16 + position * 4); z: the Q x Q matrices in global memory
@@ -191,8 +269,16 @@ __device__ __forceinline__ void pencil(const T (&v)[ZP], T (&o)[ZP], int mat, co
     T cc[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) cc[m] = cxy[c0 + m];
+    // one block per pencil on Q2 levels.  On Q3 levels the four inputs and
+    // four results it holds at once cost the fourth wave per SIMD; capped to
+    // four waves it spilled and ran 0.39-0.42 ms against 0.33-0.36 ms with one
+    // block per value (cell kernel, C5 finest level)
+    if constexpr (__is_same(T, float) && ZP == 3) {
+      pencil_contract_f32<DIR, ZP>(v, o, cc);
+    } else {
 #pragma unroll
-    for (int z = 0; z < ZP; ++z) o[z] = lane_contract<DIR>(v[z], cc);
+      for (int z = 0; z < ZP; ++z) o[z] = lane_contract<DIR>(v[z], cc);
+    }
   }
 }
 
