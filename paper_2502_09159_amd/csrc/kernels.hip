@@ -1381,8 +1381,8 @@ static hipError_t vanka_fact_impl(const LevelArgs& L, const T* Asw, const T* Bm,
 }
 
 template <typename T>
-hipError_t launch_vanka_gather_only(const LevelArgs& L, const T* E, T* x, T omega, hipStream_t s) {
-  return vanka_gather<T>(L, E, x, omega, s);
+hipError_t launch_vanka_gather_only(const LevelArgs& L, const T* E, T* x, T omega, hipStream_t s, bool xzero) {
+  return vanka_gather<T>(L, E, x, omega, s, xzero);
 }
 
 template <typename T>
@@ -2922,7 +2922,7 @@ hipError_t launch_project_pressure(const LevelArgs& L, const double* mom, double
   template hipError_t launch_restrict<T>(const LevelArgs&, const LevelArgs&, const TransferDev&, const T*,         \
                                          const int*, const int*, const T*, const T*, const T*, T*, T*, T*, T*,      \
                                          hipStream_t);                                                              \
-  template hipError_t launch_vanka_gather_only<T>(const LevelArgs&, const T*, T*, T, hipStream_t);                \
+  template hipError_t launch_vanka_gather_only<T>(const LevelArgs&, const T*, T*, T, hipStream_t, bool);                \
   template hipError_t launch_coarse<T>(int64_t, int64_t, int, int, const double*, const double*, const T*, T*,  \
                                         hipStream_t);                          \
   template hipError_t launch_fill<T>(T*, T, int64_t, hipStream_t);                                                  \

@@ -109,9 +109,12 @@ template <typename T>
 hipError_t launch_vanka_decoupled(const LevelArgs& L, const T* Aw, const T* Bm, const T* Ft, const T* Ht,
                                   const T* tw, const T* r, T* x, T omega, T* E, hipStream_t s,
                                   bool gather = true, bool xzero = false, bool diagonal = false);
-// x_v += omega / valence * sum_cells E (the velocity half of a patch update).
+// x_v += omega / valence * sum_cells E (the velocity half of a patch update);
+// xzero: x_v holds no values yet, x_v = omega / valence * sum_cells E (0 on
+// Dirichlet nodes).
 template <typename T>
-hipError_t launch_vanka_gather_only(const LevelArgs& L, const T* E, T* x, T omega, hipStream_t s);
+hipError_t launch_vanka_gather_only(const LevelArgs& L, const T* E, T* x, T omega, hipStream_t s,
+                                    bool xzero = false);
 // Same with one dense local inverse per cell.
 template <typename T>
 hipError_t launch_vanka_dense(const LevelArgs& L, const T* Ainv, const T* r, T* x, T omega, hipStream_t s);

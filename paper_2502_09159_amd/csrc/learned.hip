@@ -339,12 +339,14 @@ __global__ __launch_bounds__(64) void k_net_inputs(LevelArgs L, const T* __restr
   }
 }
 
-// velocity correction s_T * y (masked) into E (Vanka scratch layout), pressure added to x
+// velocity correction s_T * y (masked) into E (Vanka scratch layout), pressure
+// added to x (assign: written to x, which then holds no values yet)
 template <typename T>
 __global__ __launch_bounds__(64) void k_net_correction(LevelArgs L, const float* __restrict__ y,
                                                        const float* __restrict__ scale,
                                                        const float* __restrict__ mask, int64_t first,
-                                                       int64_t count, T* __restrict__ E, T* __restrict__ x) {
+                                                       int64_t count, T* __restrict__ E, T* __restrict__ x,
+                                                       int assign) {
   const int64_t sidx = blockIdx.x;
   if (sidx >= count) return;
   const int64_t smp = first + sidx, ncell = L.Mp / L.C;
@@ -364,7 +366,8 @@ __global__ __launch_bounds__(64) void k_net_correction(LevelArgs L, const float*
     float m = 0.0f;
     for (int p = 0; p < 27; ++p) m += ys[p * 16 + 6 + lane];
     int a = lane / 4, l = lane % 4;
-    x[(int64_t)n * L.slab + 2 * L.Mv + a * L.Mp + cell * L.C + l] += (T)(s * m / 27.0f);
+    T& xp = x[(int64_t)n * L.slab + 2 * L.Mv + a * L.Mp + cell * L.C + l];
+    xp = (assign ? T(0) : xp) + (T)(s * m / 27.0f);
   }
 }
 
@@ -471,8 +474,9 @@ hipError_t net_forward(NetDev& N, int64_t count, hipStream_t s, bool keep) {
 }
 
 template <typename T>
-hipError_t net_correction(const LevelArgs& L, NetDev& N, int64_t first, int64_t count, T* E, T* x, hipStream_t s) {
-  k_net_correction<T><<<(unsigned)count, 64, 0, s>>>(L, N.y, N.scale, N.mask, first, count, E, x);
+hipError_t net_correction(const LevelArgs& L, NetDev& N, int64_t first, int64_t count, T* E, T* x, hipStream_t s,
+                          bool assign) {
+  k_net_correction<T><<<(unsigned)count, 64, 0, s>>>(L, N.y, N.scale, N.mask, first, count, E, x, assign ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -503,7 +507,8 @@ template hipError_t net_inputs<double>(const LevelArgs&, NetDev&, const double*,
 template hipError_t net_inputs<float>(const LevelArgs&, NetDev&, const float*, const float*, int64_t, int64_t,
                                       hipStream_t);
 template hipError_t net_correction<double>(const LevelArgs&, NetDev&, int64_t, int64_t, double*, double*,
-                                           hipStream_t);
-template hipError_t net_correction<float>(const LevelArgs&, NetDev&, int64_t, int64_t, float*, float*, hipStream_t);
+                                           hipStream_t, bool);
+template hipError_t net_correction<float>(const LevelArgs&, NetDev&, int64_t, int64_t, float*, float*, hipStream_t,
+                                          bool);
 
 }  // namespace stmg

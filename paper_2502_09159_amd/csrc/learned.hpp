@@ -50,9 +50,11 @@ hipError_t net_inputs(const LevelArgs& L, NetDev& N, const T* r, const T* e, int
 hipError_t net_forward(NetDev& N, int64_t count, hipStream_t s, bool keep);
 
 // Correction head: cell-local velocity corrections (times s_T) into E
-// (the Vanka scratch layout) and pressure corrections added to x.
+// (the Vanka scratch layout) and pressure corrections added to x (assign:
+// written to x, whose pressure entries then need no initial values).
 template <typename T>
-hipError_t net_correction(const LevelArgs& L, NetDev& N, int64_t first, int64_t count, T* E, T* x, hipStream_t s);
+hipError_t net_correction(const LevelArgs& L, NetDev& N, int64_t first, int64_t count, T* E, T* x, hipStream_t s,
+                          bool assign = false);
 
 // Loss of the head against the targets; writes dL/dy into the workspace and
 // accumulates sum |head - t|^2 and sum |t|^2 into red[0], red[1].

@@ -515,18 +515,19 @@ Hier<double>& hier_of<double>(stmg_ctx* c) { return c->H64; }
 template <>
 Hier<float>& hier_of<float>(stmg_ctx* c) { return c->H32; }
 
-// u (velocity into E then gathered with weight 1, pressure added) += net correction of r
+// x = net(r) on level D (zero_start: x holds no values yet), or x += net(r):
+// velocity into E, then gathered with weight 1; pressure written or added
 template <typename T>
-void net_correct(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x) {
+void net_correct(stmg_ctx* c, DevLevel<T>& D, const T* r, T* x, bool zero_start) {
   const int64_t total = (int64_t)D.a.N * (D.a.Mp / D.a.C);
   const int64_t chunk = c->opt_net_chunk > 0 ? std::min<int64_t>(c->opt_net_chunk, kNetChunk) : kNetChunk;
   for (int64_t first = 0; first < total; first += chunk) {
     int64_t cnt = std::min<int64_t>(chunk, total - first);
     HIPCHK(net_inputs<T>(D.a, c->net, r, (const T*)nullptr, first, cnt, c->stream));
     HIPCHK(net_forward(c->net, cnt, c->stream, false));
-    HIPCHK(net_correction<T>(D.a, c->net, first, cnt, D.E, x, c->stream));
+    HIPCHK(net_correction<T>(D.a, c->net, first, cnt, D.E, x, c->stream, zero_start));
   }
-  HIPCHK(launch_vanka_gather_only<T>(D.a, D.E, x, T(1), c->stream));
+  HIPCHK(launch_vanka_gather_only<T>(D.a, D.E, x, T(1), c->stream, zero_start));
 }
 
 template <typename T>
@@ -543,17 +544,16 @@ template <typename T>
 void learned_correction_at(stmg_ctx* c, int level, int route, const T* r, T* cv) {
   Hier<T>& H = hier_of<T>(c);
   DevLevel<T>& D = H.L[level];
-  HIPCHK(launch_fill<T>(cv, T(0), D.ndofs, c->stream));
   if (route == 1) {
-    net_correct<T>(c, D, r, cv);
+    net_correct<T>(c, D, r, cv, true);
     return;
   }
+  HIPCHK(launch_fill<T>(cv, T(0), D.ndofs, c->stream));
   DevLevel<T>& Cl = H.L[level + 1];
   T* rc = static_cast<T*>(c->lsave[2 * (level + 1)]);
   T* cc = static_cast<T*>(c->lsave[2 * (level + 1) + 1]);
   op_restrict<T>(c, H, level, r, rc);
-  HIPCHK(launch_fill<T>(cc, T(0), Cl.ndofs, c->stream));
-  net_correct<T>(c, Cl, rc, cc);
+  net_correct<T>(c, Cl, rc, cc, true);
   op_prolongate_add<T>(c, H, level, cc, cv);
 }
 
