@@ -1126,33 +1126,35 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
   };
 
   // ---- R in B-operand order, B and the pressure residual.  R is read one
-  // x-row of a cell (Q consecutive nodes, one vector load) per item: items
-  // (n, comp, row, a), n fastest (so that the 16-byte LDS stores of a wave
-  // spread over all banks); Dirichlet entries are zeroed in registers.  Padding
+  // x-row of a cell (Q consecutive nodes, one vector load) of every temporal
+  // dof per item: items (n, comp, row), n fastest (so that the 16-byte LDS
+  // stores of a wave spread over all banks), the index work shared by the
+  // temporal dofs; Dirichlet entries are zeroed in registers.  Padding
   // entries of R (K >= M or column >= d N) are zeroed separately.  Loads
   // complete in issue order, so the loads this phase waits for are issued
   // first, then the A_s^{-1} fragments of the first row tile (consumed only
   // after the barrier).
   {
-    constexpr int ROWS = NL / Q;                           // x-rows of a cell
-    constexpr int IMAX = (ROWS * NT * D * 8 + 255) / 256;  // items per thread (N <= 8)
+    constexpr int ROWS = NL / Q;                      // x-rows of a cell
+    constexpr int IMAX = (ROWS * D * 8 + 255) / 256;  // items per thread (N <= 8)
     constexpr int PB = (C * D * NL + 255) / 256;
-    const int nitems = ROWS * NT * DN;
+    const int nitems = ROWS * DN;
     const T* Bc = Bm + cell * (int64_t)C * D * NL;
-    T rv[IMAX][Q], bv[PB];
+    T rv[IMAX][NT][Q], bv[PB];
     bool rok[IMAX];
     // unconditional loads from clamped (in-bounds) addresses, selected later:
     // the wait counts before the first LDS store then stay exact
 #pragma unroll
     for (int e = 0; e < IMAX; ++e) {
       const int it = min(tid + 256 * e, nitems - 1);
-      const int n = it & (N - 1), rest = (it >> lgN) / D, comp = (it >> lgN) - rest * D;
-      const int row = rest % ROWS, a = rest / ROWS;
+      const int n = it & (N - 1), rest = it >> lgN, comp = rest % D, row = rest / D;
       const int iy = row % Q, iz = row / Q;
       const int gy = cc[1] * (Q - 1) + iy, gz = D == 3 ? cc[2] * (Q - 1) + iz : 1;
       rok[e] = tid + 256 * e < nitems && gy > 0 && gy < L.nn - 1 && gz > 0 && (D == 2 || gz < L.nn - 1);
       const int64_t g = (int64_t)cc[0] * (Q - 1) + (int64_t)L.nn * (gy + (D == 3 ? (int64_t)L.nn * gz : 0));
-      __builtin_memcpy(rv[e], r + vidx(L, n, a, comp, g), sizeof(T) * Q);
+      const T* rp = r + vidx(L, n, 0, comp, g);
+#pragma unroll
+      for (int a = 0; a < NT; ++a) __builtin_memcpy(rv[e][a], rp + (int64_t)a * L.Mv, sizeof(T) * Q);
     }
 #pragma unroll
     for (int e = 0; e < PB; ++e) bv[e] = Bc[min(tid + 256 * e, C * D * NL - 1)];
@@ -1180,19 +1182,20 @@ __global__ __launch_bounds__(256) void k_vanka_mfma(LevelArgs L, const T* __rest
     for (int e = 0; e < IMAX; ++e) {
       const int it = tid + 256 * e;
       if (it < nitems) {
-        const int n = it & (N - 1), rest = (it >> lgN) / D, comp = (it >> lgN) - rest * D;
-        const int row = rest % ROWS, a = rest / ROWS, col = comp * N + n;
-        const int K0 = a * NL + row * Q;
+        const int n = it & (N - 1), rest = it >> lgN, comp = rest % D, row = rest / D, col = comp * N + n;
         const int ct = col / 16, jj = col % 16;
         // Dirichlet rows, and Dirichlet nodes at the ends of the row (x = 0, x = 1)
+        bool zero[Q];
 #pragma unroll
         for (int j = 0; j < Q; ++j)
-          if (!rok[e] || (j == 0 && cc[0] == 0) || (j == Q - 1 && cc[0] == L.n - 1)) rv[e][j] = T(0);
+          zero[j] = !rok[e] || (j == 0 && cc[0] == 0) || (j == Q - 1 && cc[0] == L.n - 1);
 #pragma unroll
-        for (int j = 0; j < Q; ++j) {
-          const int K = K0 + j, kb = K / 16, rem = K % 16;
-          RZ[((ct * NKB + kb) * 64 + jj + 16 * (rem / 4)) * 4 + (rem % 4)] = rv[e][j];
-        }
+        for (int a = 0; a < NT; ++a)
+#pragma unroll
+          for (int j = 0; j < Q; ++j) {
+            const int K = a * NL + row * Q + j, kb = K / 16, rem = K % 16;
+            RZ[((ct * NKB + kb) * 64 + jj + 16 * (rem / 4)) * 4 + (rem % 4)] = zero[j] ? T(0) : rv[e][a][j];
+          }
       }
     }
 #pragma unroll
