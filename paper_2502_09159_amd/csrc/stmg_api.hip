@@ -1126,17 +1126,24 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
     int total = 0, applications = 0, fallbacks = 0;
     double rel = 0.0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hv(m + 2), y(m);
+    bool x_zero = true;
     while (true) {
-      // explicit residual
-      if (c->phase_timing) c->t_op.a(s);
-      op_apply<double>(c, L0, x, b, c->w, 1);
-      if (c->phase_timing) c->t_op.b(s);
-      double beta = std::sqrt(dot(c, c->w, c->w, n));
+      // explicit residual (b itself while x is still 0: b - S 0 = b exactly,
+      // Dirichlet rows included)
+      const double* r0 = b;
+      double beta = bnorm;
+      if (!x_zero) {
+        if (c->phase_timing) c->t_op.a(s);
+        op_apply<double>(c, L0, x, b, c->w, 1);
+        if (c->phase_timing) c->t_op.b(s);
+        beta = std::sqrt(dot(c, c->w, c->w, n));
+        r0 = c->w;
+      }
       rel = bnorm > 0 ? beta / bnorm : 0.0;
       c->history.push_back(rel);
       if (bnorm == 0.0 || beta <= rtol * bnorm || total >= max_it) break;
       // (mixed: the FP32 copy of V_0 is the first V-cycle's input)
-      HIPCHK(launch_scale_copy(c->V, c->w, 1.0 / beta, n, s, c->mixed ? c->H32.L[0].b : nullptr));
+      HIPCHK(launch_scale_copy(c->V, r0, 1.0 / beta, n, s, c->mixed ? c->H32.L[0].b : nullptr));
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       int j = 0;
@@ -1247,6 +1254,7 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
       HIPCHK(hipMemcpyAsync(c->dh, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
       if (c->mixed) HIPCHK(launch_combine_f32(x, c->Z32, ldv, j, c->dh, n, s));
       else HIPCHK(launch_combine(x, c->Z, ldv, j, c->dh, n, s));
+      x_zero = false;
     }
     HIPCHK(launch_project_pressure(L0.a, c->mom0, c->volume0, x, c->partial, s));
     HIPCHK(hipEventRecord(e1, s));
