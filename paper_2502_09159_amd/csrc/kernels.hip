@@ -2841,26 +2841,27 @@ hipError_t launch_lcgs2(double* V, int64_t ldv, int j, int pending, const double
   return hipGetLastError();
 }
 
+// w += sign sum_k h_k V_k (assign: w = sign sum_k h_k V_k, w not read)
 __global__ void k_multi_axpy(double* __restrict__ w, const double* __restrict__ V, int64_t ldv, int nv,
-                             const double* __restrict__ h, int64_t n, double sign) {
+                             const double* __restrict__ h, int64_t n, double sign, int assign) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
   for (int k = 0; k < nv; ++k) s += h[k] * V[(int64_t)k * ldv + i];
-  w[i] += sign * s;
+  w[i] = (assign ? 0.0 : w[i]) + sign * s;
 }
 hipError_t launch_multi_axpy(double* w, const double* V, int64_t ldv, int nv, const double* h, int64_t n,
                              hipStream_t s) {
-  k_multi_axpy<<<nblk(n), 256, 0, s>>>(w, V, ldv, nv, h, n, -1.0);
+  k_multi_axpy<<<nblk(n), 256, 0, s>>>(w, V, ldv, nv, h, n, -1.0, 0);
   return hipGetLastError();
 }
 hipError_t launch_combine(double* x, const double* Z, int64_t ldz, int nv, const double* y, int64_t n,
-                          hipStream_t s) {
-  k_multi_axpy<<<nblk(n), 256, 0, s>>>(x, Z, ldz, nv, y, n, 1.0);
+                          hipStream_t s, bool assign) {
+  k_multi_axpy<<<nblk(n), 256, 0, s>>>(x, Z, ldz, nv, y, n, 1.0, assign ? 1 : 0);
   return hipGetLastError();
 }
 __global__ void k_combine_f32(double* __restrict__ x, const float* __restrict__ Z, int64_t ldz, int nv,
-                              const double* __restrict__ y, int64_t n) {
+                              const double* __restrict__ y, int64_t n, int assign) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   // 8 basis loads in flight at a time (indices past nv read the last vector, weight 0)
@@ -2872,11 +2873,11 @@ __global__ void k_combine_f32(double* __restrict__ x, const float* __restrict__ 
 #pragma unroll
     for (int k = 0; k < 8; ++k) s += (k0 + k < nv ? y[k0 + k] : 0.0) * (double)z[k];
   }
-  x[i] += s;
+  x[i] = (assign ? 0.0 : x[i]) + s;
 }
 hipError_t launch_combine_f32(double* x, const float* Z, int64_t ldz, int nv, const double* y, int64_t n,
-                              hipStream_t s) {
-  k_combine_f32<<<nblk(n), 256, 0, s>>>(x, Z, ldz, nv, y, n);
+                              hipStream_t s, bool assign) {
+  k_combine_f32<<<nblk(n), 256, 0, s>>>(x, Z, ldz, nv, y, n, assign ? 1 : 0);
   return hipGetLastError();
 }
 __global__ void k_scale_copy(double* y, const double* x, double inv, int64_t n, float* y32) {

@@ -192,11 +192,12 @@ hipError_t launch_lcgs2(double* V, int64_t ldv, int j, int pending, const double
 // w -= sum_i h_i V_i (h on device)
 hipError_t launch_multi_axpy(double* w, const double* V, int64_t ldv, int nv, const double* h, int64_t n,
                              hipStream_t s);
-// x += sum_i y_i Z_i (FP64 basis, or FP32 basis)
+// x += sum_i y_i Z_i (FP64 basis, or FP32 basis); assign: x = sum_i y_i Z_i
+// (x not read)
 hipError_t launch_combine(double* x, const double* Z, int64_t ldz, int nv, const double* y, int64_t n,
-                          hipStream_t s);
+                          hipStream_t s, bool assign = false);
 hipError_t launch_combine_f32(double* x, const float* Z, int64_t ldz, int nv, const double* y, int64_t n,
-                              hipStream_t s);
+                              hipStream_t s, bool assign = false);
 // scale: y = x * inv (and y32 = y rounded to FP32, when y32 is given)
 hipError_t launch_scale_copy(double* y, const double* x, double inv, int64_t n, hipStream_t s,
                              float* y32 = nullptr);

@@ -1121,7 +1121,6 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, s));
-    HIPCHK(launch_fill<double>(x, 0.0, n, s));
     double bnorm = std::sqrt(dot(c, b, b, n));
     int total = 0, applications = 0, fallbacks = 0;
     double rel = 0.0;
@@ -1141,7 +1140,10 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
       }
       rel = bnorm > 0 ? beta / bnorm : 0.0;
       c->history.push_back(rel);
-      if (bnorm == 0.0 || beta <= rtol * bnorm || total >= max_it) break;
+      if (bnorm == 0.0 || beta <= rtol * bnorm || total >= max_it) {
+        if (x_zero) HIPCHK(launch_fill<double>(x, 0.0, n, s));
+        break;
+      }
       // (mixed: the FP32 copy of V_0 is the first V-cycle's input)
       HIPCHK(launch_scale_copy(c->V, r0, 1.0 / beta, n, s, c->mixed ? c->H32.L[0].b : nullptr));
       std::fill(g.begin(), g.end(), 0.0);
@@ -1252,8 +1254,9 @@ stmg_status stmg_solve(stmg_ctx* c, const double* b, double* x, double rtol, int
         y[i] = t / H[(size_t)i * m + i];
       }
       HIPCHK(hipMemcpyAsync(c->dh, y.data(), j * sizeof(double), hipMemcpyHostToDevice, s));
-      if (c->mixed) HIPCHK(launch_combine_f32(x, c->Z32, ldv, j, c->dh, n, s));
-      else HIPCHK(launch_combine(x, c->Z, ldv, j, c->dh, n, s));
+      // (x = 0 before the first combination: it is written, not read)
+      if (c->mixed) HIPCHK(launch_combine_f32(x, c->Z32, ldv, j, c->dh, n, s, x_zero));
+      else HIPCHK(launch_combine(x, c->Z, ldv, j, c->dh, n, s, x_zero));
       x_zero = false;
     }
     HIPCHK(launch_project_pressure(L0.a, c->mom0, c->volume0, x, c->partial, s));
