@@ -633,9 +633,27 @@ void precondition(stmg_ctx* c, const double* v, double* z) {
     HIPCHK(launch_cast_f2d(D.x, z, D.ndofs, c->stream));
   } else {
     DevLevel<double>& D = c->H64.L[0];
-    HIPCHK(hipMemcpyAsync(D.b, v, D.ndofs * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    vcycle<double>(c, c->H64, 0);
-    HIPCHK(hipMemcpyAsync(z, D.x, D.ndofs * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (v != z) {
+      // the V-cycle reads the finest level's b and writes its x: run it on v
+      // and z themselves (b is only read on the finest level)
+      struct Restore {
+        double*& b;
+        double*& x;
+        double* kb;
+        double* kx;
+        ~Restore() {
+          b = kb;
+          x = kx;
+        }
+      } restore{D.b, D.x, D.b, D.x};
+      D.b = const_cast<double*>(v);
+      D.x = z;
+      vcycle<double>(c, c->H64, 0);
+    } else {
+      HIPCHK(hipMemcpyAsync(D.b, v, D.ndofs * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      vcycle<double>(c, c->H64, 0);
+      HIPCHK(hipMemcpyAsync(z, D.x, D.ndofs * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    }
   }
   if (c->phase_timing) c->t_vcyc.b(c->stream);
 }
