@@ -266,19 +266,22 @@ __global__ void k_net_pack(const float* __restrict__ w, uint16_t* __restrict__ f
 }
 
 // ------------------------------------------------------------ inputs / head
-// One wave per sample (n, cell) of a Q2/P1 x DG(1) level.
+// One wave per sample (n, cell) of a Q2/P1 x DG(1) level, four samples per
+// work group (a quarter of the work groups of one per sample).
 template <typename T>
-__global__ __launch_bounds__(64) void k_net_inputs(LevelArgs L, const T* __restrict__ r, const T* __restrict__ e,
-                                                   int64_t first, int64_t count, uint16_t* __restrict__ x,
-                                                   float* __restrict__ scale, float* __restrict__ mask,
-                                                   float* __restrict__ tv, float* __restrict__ tp) {
-  const int64_t sidx = blockIdx.x;
-  if (sidx >= count) return;
-  const int64_t smp = first + sidx, ncell = L.Mp / L.C;
+__global__ __launch_bounds__(256) void k_net_inputs(LevelArgs L, const T* __restrict__ r, const T* __restrict__ e,
+                                                    int64_t first, int64_t count, uint16_t* __restrict__ x,
+                                                    float* __restrict__ scale, float* __restrict__ mask,
+                                                    float* __restrict__ tv, float* __restrict__ tp) {
+  const int wave = threadIdx.x / 64;
+  const int64_t sidx = (int64_t)blockIdx.x * 4 + wave;
+  if (sidx >= count) return;  // (uniform over the wave; the work group has no barrier)
+  const int64_t smp = first + sidx, ncell = n_cells(L);
   const int n = (int)(smp / ncell);
-  const int64_t cell = smp % ncell;
-  const int lane = threadIdx.x, p = lane;
-  int cc[3] = {(int)(cell % L.n), (int)((cell / L.n) % L.n), (int)(cell / ((int64_t)L.n * L.n))};
+  const int64_t cell = smp - (int64_t)n * ncell;
+  const int lane = threadIdx.x % 64, p = lane;
+  int cc[3];
+  cell_coords(L, cell, cc);
   bool fr = false;
   int64_t g = 0;
   if (p < 27) {
@@ -309,11 +312,12 @@ __global__ __launch_bounds__(64) void k_net_inputs(LevelArgs L, const T* __restr
   }
   for (int off = 32; off > 0; off >>= 1) ssq += __shfl_xor(ssq, off, 64);
   const float s = sqrtf(ssq), inv = s > 0.0f ? 1.0f / s : 0.0f;
-  __shared__ float sp[8];
-  if (lane < 8) sp[lane] = pres * inv;
-  __syncthreads();
+  float sp[8];  // the 8 pressure inputs, from lanes 0..7
+#pragma unroll
+  for (int c = 0; c < 8; ++c) sp[c] = __shfl(pres * inv, c, 64);
   uint16_t* xs = x + sidx * 512;
   if (p < 32) {
+#pragma unroll
     for (int c = 0; c < 16; ++c) {
       float v = 0.0f;
       if (p < 27) {
@@ -342,17 +346,17 @@ __global__ __launch_bounds__(64) void k_net_inputs(LevelArgs L, const T* __restr
 // velocity correction s_T * y (masked) into E (Vanka scratch layout), pressure
 // added to x (assign: written to x, which then holds no values yet)
 template <typename T>
-__global__ __launch_bounds__(64) void k_net_correction(LevelArgs L, const float* __restrict__ y,
-                                                       const float* __restrict__ scale,
-                                                       const float* __restrict__ mask, int64_t first,
-                                                       int64_t count, T* __restrict__ E, T* __restrict__ x,
-                                                       int assign) {
-  const int64_t sidx = blockIdx.x;
+__global__ __launch_bounds__(256) void k_net_correction(LevelArgs L, const float* __restrict__ y,
+                                                        const float* __restrict__ scale,
+                                                        const float* __restrict__ mask, int64_t first,
+                                                        int64_t count, T* __restrict__ E, T* __restrict__ x,
+                                                        int assign) {
+  const int64_t sidx = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;  // one wave per sample
   if (sidx >= count) return;
-  const int64_t smp = first + sidx, ncell = L.Mp / L.C;
+  const int64_t smp = first + sidx, ncell = n_cells(L);
   const int n = (int)(smp / ncell);
-  const int64_t cell = smp % ncell;
-  const int lane = threadIdx.x;
+  const int64_t cell = smp - (int64_t)n * ncell;
+  const int lane = threadIdx.x % 64;
   const float s = scale[sidx];
   const float* ys = y + sidx * 512;
   if (lane < 27) {
@@ -458,7 +462,8 @@ template <typename T>
 hipError_t net_inputs(const LevelArgs& L, NetDev& N, const T* r, const T* e, int64_t first, int64_t count,
                       hipStream_t s) {
   if (count > N.cap || L.d != 3 || L.Q != 3 || L.nt != 2) return hipErrorInvalidValue;
-  k_net_inputs<T><<<(unsigned)count, 64, 0, s>>>(L, r, e, first, count, N.x, N.scale, N.mask, N.tv, N.tp);
+  k_net_inputs<T><<<(unsigned)((count + 3) / 4), 256, 0, s>>>(L, r, e, first, count, N.x, N.scale, N.mask, N.tv,
+                                                               N.tp);
   return hipGetLastError();
 }
 
@@ -476,7 +481,8 @@ hipError_t net_forward(NetDev& N, int64_t count, hipStream_t s, bool keep) {
 template <typename T>
 hipError_t net_correction(const LevelArgs& L, NetDev& N, int64_t first, int64_t count, T* E, T* x, hipStream_t s,
                           bool assign) {
-  k_net_correction<T><<<(unsigned)count, 64, 0, s>>>(L, N.y, N.scale, N.mask, first, count, E, x, assign ? 1 : 0);
+  k_net_correction<T><<<(unsigned)((count + 3) / 4), 256, 0, s>>>(L, N.y, N.scale, N.mask, first, count, E, x,
+                                                                  assign ? 1 : 0);
   return hipGetLastError();
 }
 
