@@ -82,13 +82,15 @@ def vanka_local_bytes(w, elem_bytes):
       coupled (k_vanka_mfma): A_s^{-1} padded to 16 (mp^2, m = (k+1) nl),
         B (C d nl), F (d m P), H^{-1} (P^2), P = (k+1) C;
       decoupled (k_vanka_tdec): the k+1 real nl x nl blocks (padded to 16) of
-        the real and complex spatial inverses, B, F (J d nl complex) and
-        H^{-1} (J C^2 complex), J = ceil((k+1)/2) blocks."""
+        the real and complex spatial inverses, each symmetric and stored as
+        its upper 16 x 16 tiles (nkb (nkb + 1) / 2 of them, nkb = nl / 16
+        rounded up), B, F (J d nl complex) and H^{-1} (J C^2 complex),
+        J = ceil((k+1)/2) blocks."""
     d, nl, nt, C, N, ncells, ndofs = element_sizes(w)
     if vanka_form(w) == "decoupled":
-        nlp = (nl + 15) // 16 * 16
+        nkb = (nl + 15) // 16
         J = (nt + 1) // 2
-        factors = nt * nlp * nlp + C * d * nl + J * d * nl * 2 * C + J * C * 2 * C
+        factors = nt * nkb * (nkb + 1) // 2 * 256 + C * d * nl + J * d * nl * 2 * C + J * C * 2 * C
     else:
         m, P = nt * nl, nt * C
         mp = (m + 15) // 16 * 16

@@ -114,6 +114,37 @@ __device__ __forceinline__ double dpp(double v) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// v from lane src (any lane of the wave)
+__device__ __forceinline__ float lane_read(float v, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src << 2, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double lane_read(double v, int src) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(src << 2, (int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Transposes, in place, a 16 x 16 tile held in MFMA operand order: lane
+// i + 16 g, slot s holds entry [i][4 g + s]; afterwards it holds [4 g + s][i].
+// With row = 4 r1 + r0 and column = 4 c1 + c0, entry [row][column] sits in
+// lane bits (5:4, 3:2, 1:0) = (c1, r1, r0) and slot c0, and its transpose in
+// (r1, c1, c0) and slot r0: a 4 x 4 transpose of (lane bits 1:0, slot) inside
+// every quad of lanes (two butterfly stages, on lane bit 0 and lane bit 1),
+// then the exchange of lane bits 5:4 and 3:2 across the wave.
+template <typename T>
+__device__ __forceinline__ void tile_transpose16(T (&v)[4], int lane) {
+  const bool b0 = lane & 1, b1 = lane & 2;
+  const T d0 = dpp<kQuadSwap1>(v[0]), d1 = dpp<kQuadSwap1>(v[1]);
+  const T d2 = dpp<kQuadSwap1>(v[2]), d3 = dpp<kQuadSwap1>(v[3]);
+  const T n0 = b0 ? d1 : v[0], n1 = b0 ? v[1] : d0, n2 = b0 ? d3 : v[2], n3 = b0 ? v[3] : d2;
+  const T e0 = dpp<kQuadRot2>(n0), e1 = dpp<kQuadRot2>(n1), e2 = dpp<kQuadRot2>(n2), e3 = dpp<kQuadRot2>(n3);
+  const T q[4] = {b1 ? e2 : n0, b1 ? e3 : n1, b1 ? n2 : e0, b1 ? n3 : e1};
+  const int src = (((lane >> 2) & 3) << 4) | (((lane >> 4) & 3) << 2) | (lane & 3);
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) v[sl] = lane_read(q[sl], src);
+}
+
 // out = sum_m c[m] v(source lane of permutation m), along x (DIR 0) or y (DIR 1)
 template <int DIR, typename T>
 __device__ __forceinline__ T lane_contract(T v, const T* c) {
@@ -1420,7 +1451,9 @@ hipError_t launch_vanka_factored(const LevelArgs& L, const T* Asw, const T* Bm, 
 // per spatial cell, all N subintervals and d components at once:
 //   R~_j = sum_a T_ja R_a                 (velocity and pressure residuals)
 //   Z_j  = Ainv_j R~_j                    (matrix cores; a complex block as
-//                                          the real operands Re / Im Ainv_j)
+//                                          the real operands Re / Im Ainv_j,
+//                                          each symmetric and stored as its
+//                                          upper 16 x 16 tiles)
 //   p~_j = Hinv_j (-B Z_j - R~p_j),  u~_j = Z_j - F_j p~_j
 //   x_p[a] += omega sum_j Re(Wt_aj p~_j),  E[a] = sum_j Re(Wt_aj u~_j)
 // Columns of R~ and Z: comp N + n, padded to DNP = 16 NCT; real parts, then
@@ -1447,6 +1480,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 && NT <= 2 ? 5 : 1) void k_vank
   constexpr int J = (NT + 1) / 2, NR = NT % 2;  // blocks; block 0 is real iff NT is odd
   constexpr int DNP = NCT * 16, NCOL = 2 * DNP, ZS = NCOL + 1;
   constexpr int RT = J * NKB;                   // row tiles (16 rows of one block)
+  constexpr int NTL = NKB * (NKB + 1) / 2;      // stored (upper) tiles of one real block
   constexpr int CSPL = RT >= 4 ? 1 : 4 / RT;    // waves that share a row tile split its column tiles
   constexpr int TPW = (RT + 3) / 4;             // row tiles per wave
   constexpr int R4 = (2 * C + 3) / 4 * 4;       // vanka_tdec_row(C)
@@ -1472,21 +1506,24 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 && NT <= 2 ? 5 : 1) void k_vank
   };
 
   // ---- Ainv fragments of this wave's first row tile (issued right after
-  // the residual loads, consumed after the barrier)
-  const T* A = Aw + cell * (int64_t)(DIAG ? 2 * J * NL : NT * MP * MP);
+  // the residual loads, consumed after the barrier).  Tile (lt, kb) with
+  // kb < lt is read from its mirror (kb, lt) and transposed before use.
+  const T* A = Aw + cell * (int64_t)(DIAG ? 2 * J * NL : NT * NTL * 256);
   T fx[NKB][4], fy[NKB][4];
   auto load_tile = [&](int t) {
     if constexpr (DIAG) return;
     const int j = t / NKB, lt = t % NKB;
-    const T* X = A + (int64_t)(j < NR ? j : 2 * j - NR) * MP * MP + (int64_t)lt * NKB * 256 + lane * 4;
-    const T* Y = j < NR ? X : X + MP * MP;  // (a real block reads its Re tile twice; unused)
+    const T* X = A + (int64_t)(j < NR ? j : 2 * j - NR) * NTL * 256 + lane * 4;
+    const T* Y = j < NR ? X : X + NTL * 256;  // (a real block reads its Re tile twice; unused)
 #pragma unroll
-    for (int kb = 0; kb < NKB; ++kb)
+    for (int kb = 0; kb < NKB; ++kb) {
+      const int I = min(lt, kb), K = max(lt, kb), up = I * NKB - I * (I - 1) / 2 + (K - I);
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) {
-        fx[kb][sl] = X[kb * 256 + sl];
-        fy[kb][sl] = Y[kb * 256 + sl];
+        fx[kb][sl] = X[up * 256 + sl];
+        fy[kb][sl] = Y[up * 256 + sl];
       }
+    }
   };
   const int t_first = CSPL > 1 ? wave % RT : min(wave, RT - 1);
 
@@ -1624,7 +1661,13 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 && NT <= 2 ? 5 : 1) void k_vank
     }
     const bool active = t < RT && (CSPL == 1 || wave < RT * CSPL);
     if (active) {
-      const int j = t / NKB;
+      const int j = t / NKB, lt = t % NKB;
+#pragma unroll
+      for (int kb = 0; kb < NKB - 1; ++kb)
+        if (kb < lt) {  // (wave-uniform) a tile below the diagonal
+          tile_transpose16<T>(fx[kb], lane);
+          if (j >= NR) tile_transpose16<T>(fy[kb], lane);
+        }
       if (j >= NR) {
         T ny[NKB][4];
 #pragma unroll

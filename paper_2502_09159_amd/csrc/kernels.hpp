@@ -90,18 +90,29 @@ inline int64_t vanka_swizzle_index(int mp, int row, int k) {
 // representative per complex-conjugate pair; the block count J and the number
 // of real blocks follow from nt: J = (nt + 1) / 2, one real block iff nt is
 // odd).  Per cell:
-//   Aw: per block, Re (Ainv_j) then, for a complex block, Im (Ainv_j), each
-//       mp x mp (mp = 16 ceil(nloc / 16)) in MFMA operand order
-//       (vanka_swizzle_index);
+//   Aw: per block, Re (Ainv_j) then, for a complex block, Im (Ainv_j).  Both
+//       are symmetric (Ainv_j inverts lambda_j M + A, M and A symmetric), so
+//       each is stored as the upper triangle of its 16 x 16 tiles
+//       (mp = 16 ceil(nloc / 16); vanka_sym_index);
 //   Bm: C x d x nloc (as for the coupled factors);
 //   Ft: [j][comp][i][row] with row = (re, im) of F_j[comp][i][l] for l < C,
 //       padded to vanka_tdec_row(C) values;
 //   Ht: [j][l][row] with row = (re, im) of Hinv_j[l][l'], padded likewise;
 //   tw: per level, T (J x nt complex, (re, im)) then Wt (nt x J complex).
 inline int vanka_tdec_row(int C) { return (2 * C + 3) / 4 * 4; }
+// Position of entry (row, k), row / 16 <= k / 16, of a symmetric mp x mp block
+// stored as its tiles (I, K), I <= K, row by row, each tile in MFMA operand
+// order (lane = row%16 + 16*((k%16)/4), slot k%4, as vanka_swizzle_index).
+// The kernel reads a tile below the diagonal as the transpose of its mirror.
+inline int64_t vanka_sym_index(int mp, int row, int k) {
+  const int nkb = mp / 16, I = row / 16, K = k / 16;
+  const int up = I * nkb - I * (I - 1) / 2 + (K - I);
+  const int lane = row % 16 + 16 * ((k % 16) / 4), sl = k % 4;
+  return ((int64_t)up * 64 + lane) * 4 + sl;
+}
 inline int64_t vanka_tdec_aw(int nloc, int nt) {
-  const int64_t mp = (nloc + 15) / 16 * 16;
-  return (int64_t)nt * mp * mp;  // 2 J - nreal = nt blocks of mp^2
+  const int64_t nkb = (nloc + 15) / 16;
+  return (int64_t)nt * nkb * (nkb + 1) / 2 * 256;  // 2 J - nreal = nt blocks of upper tiles
 }
 // diagonal: the diagonal Vanka (blocks lambda_j diag(M) + diag(A)): Aw holds
 // nloc complex inverse diagonal entries per block (re, im) and Ft is unused.

@@ -275,21 +275,30 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
       for (const auto& z : V.te.T) { tw.push_back(z.real()); tw.push_back(z.imag()); }
       for (const auto& z : V.te.Wt) { tw.push_back(z.real()); tw.push_back(z.imag()); }
       D.coef = c->pool.upload<T>(tw, s);
-      const int64_t aw = vanka_tdec_aw(nl, nt);
+      const int64_t aw = vanka_tdec_aw(nl, nt), half = aw / nt;  // half: one real block's tiles
       std::vector<T> A((size_t)L.ncells * aw, T(0));
       std::vector<T> Fr((size_t)L.ncells * J * d * nl * R4, T(0)), Hr((size_t)L.ncells * J * C * R4, T(0));
-#pragma omp parallel for schedule(static)
+      int asym = 0;  // blocks whose inverse is not symmetric to rounding
+#pragma omp parallel for schedule(static) reduction(+ : asym)
       for (int64_t cl = 0; cl < L.ncells; ++cl) {
         for (int j = 0; j < J; ++j) {
           const bool cpx = j >= V.te.nreal;
-          T* X = &A[(size_t)cl * aw + (size_t)(j < V.te.nreal ? j : 2 * j - V.te.nreal) * mp * mp];
+          T* X = &A[(size_t)cl * aw + (size_t)(j < V.te.nreal ? j : 2 * j - V.te.nreal) * half];
           const std::complex<double>* Ai = &V.Ainv[((size_t)cl * J + j) * nl * nl];
+          // the upper tiles of the symmetric part (Ainv_j is symmetric up to
+          // the rounding of its inversion, which the check below bounds)
+          double amax = 0.0, dmax = 0.0;
           for (int row = 0; row < nl; ++row)
             for (int k = 0; k < nl; ++k) {
-              const std::complex<double> z = Ai[(size_t)row * nl + k];
-              X[vanka_swizzle_index(mp, row, k)] = (T)z.real();
-              if (cpx) X[(size_t)mp * mp + vanka_swizzle_index(mp, row, k)] = (T)z.imag();
+              const std::complex<double> z = Ai[(size_t)row * nl + k], zt = Ai[(size_t)k * nl + row];
+              amax = std::max(amax, std::abs(z));
+              dmax = std::max(dmax, std::abs(z - zt));
+              if (row / 16 > k / 16) continue;
+              const std::complex<double> zs = 0.5 * (z + zt);
+              X[vanka_sym_index(mp, row, k)] = (T)zs.real();
+              if (cpx) X[half + vanka_sym_index(mp, row, k)] = (T)zs.imag();
             }
+          if (!(dmax <= 1e-9 * amax)) ++asym;
           const std::complex<double>* F = &V.F[((size_t)cl * J + j) * d * nl * C];
           for (int ci = 0; ci < d * nl; ++ci)
             for (int l = 0; l < C; ++l) {
@@ -306,6 +315,7 @@ void build_hier(stmg_ctx* c, Hier<T>& H, const std::vector<VankaFactors>& VF,
             }
         }
       }
+      if (asym) throw Error(STMG_EUNSUPPORTED, "a decoupled local velocity inverse is not symmetric");
       D.Asw = c->pool.upload<T>(A, s);
       D.Bm = c->pool.upload<T>(V.Bm, s);
       D.F = c->pool.upload<T>(Fr, s);
