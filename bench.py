@@ -43,14 +43,18 @@ WORKLOADS = {
                                 "nu(x)=exp(0.5 g(x))"),
 }
 TAU, OMEGA = 0.05, 0.8
+# Vanka sweeps before and after the coarse-grid correction on the slab
+# workloads: the fastest schedule at C5 for the FP32 and the FP64 V-cycle
+# alike in a sweep over (pre, post) in {1, 2}^2 and omega in {0.6, ..., 0.95}
+PRE, POST = 1, 2
 WEIGHTS = os.path.join(ROOT, "paper_2502_09159_amd", "weights", "net_c4.npy")
 
 
 def solver_params(w, precision):
     keys = ("dim", "n_cells_1d", "n_coarse_1d", "r", "k", "n_sub", "deform_amp", "k_min", "placement")
     p = {k: w[k] for k in keys if k in w}
-    p.update(tau=TAU, nu=1.0, omega=OMEGA, precision=precision)
-    p.update(nu_pre=w.get("nsm", 1), nu_post=w.get("nsm", 1), local_solver=w.get("local_solver", 0))
+    p.update(tau=TAU, nu=1.0, omega=w.get("omega", OMEGA), precision=precision)
+    p.update(nu_pre=w.get("pre", PRE), nu_post=w.get("post", POST), local_solver=w.get("local_solver", 0))
     return p
 
 
@@ -184,7 +188,8 @@ def cpu_baseline(w, n):
     nu = FourierViscosity(w["nu_seed"]) if "nu_seed" in w else 1.0
     t0 = time.perf_counter()
     mg = Multigrid(w["dim"], n, w["r"], w["k"], w["n_sub"], TAU, nu=nu, amp=w["deform_amp"], n_coarse=2,
-                   k_min=w["k_min"], omega=OMEGA, placement="top" if w.get("placement", 0) == 1 else "paper")
+                   k_min=w["k_min"], omega=w.get("omega", OMEGA), nu_pre=w.get("pre", PRE),
+                   nu_post=w.get("post", POST), placement="top" if w.get("placement", 0) == 1 else "paper")
     setup = time.perf_counter() - t0
     L = mg.levels[0]
     b = random_rhs(w["dim"], n, w["r"], w["k"], w["n_sub"], w["seed"])
@@ -298,8 +303,12 @@ def main():
     ap.add_argument("--lid-c", type=int, default=4, help="refinement level c of the lid-driven cavity")
     ap.add_argument("--variant", default="learned", choices=["learned", "mixed", "fp64"])
     ap.add_argument("--weights", default=WEIGHTS, help="trained network (from paper_2502_09159_amd.train_c4)")
-    ap.add_argument("--nsm", type=int, default=2,
-                    help="Vanka sweeps before and after the coarse correction (n_sm of Tables 3 and 4)")
+    ap.add_argument("--nsm", type=int, default=None,
+                    help="Vanka sweeps before and after the coarse correction (n_sm of Tables 3 and 4; default "
+                         f"{PRE} before and {POST} after on the slab workloads, 2 and 2 for the lid-driven cavity)")
+    ap.add_argument("--pre", type=int, default=None, help="Vanka sweeps before the coarse correction")
+    ap.add_argument("--post", type=int, default=None, help="Vanka sweeps after the coarse correction")
+    ap.add_argument("--omega", type=float, default=OMEGA, help="Vanka relaxation")
     ap.add_argument("--local-solver", default="exact", choices=["exact", "diagonal"],
                     help="exact patch inverses or the diagonal Vanka")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -316,6 +325,8 @@ def main():
         sys.exit(2)
 
     if args.workload == "lid":
+        if args.nsm is None:
+            args.nsm = 2
         run_lid(args)
         return
 
@@ -331,7 +342,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = dict(WORKLOADS[args.workload])
-    w["nsm"] = args.nsm
+    w["pre"] = args.pre if args.pre is not None else (args.nsm if args.nsm is not None else PRE)
+    w["post"] = args.post if args.post is not None else (args.nsm if args.nsm is not None else POST)
+    w["omega"] = args.omega
     w["local_solver"] = 1 if args.local_solver == "diagonal" else 0
     if args.max_it is None:
         args.max_it = 600 if args.workload == "c4" else 200
@@ -453,7 +466,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["label"], "ndofs": ndofs, "variant": args.variant,
                    "solver": f"FGMRES(CGS2) + hp space-time MG V-cycle, {args.local_solver} cell Vanka "
-                             f"({args.nsm} pre/{args.nsm} post), omega 0.8"
+                             f"({w['pre']} pre/{w['post']} post), omega {w['omega']}"
                              + (", learned correction on Q2/P1 x DG(1) levels" if args.variant == "learned" else ""),
                    "iterations": its[-1], "rel_residual": rel_final, "setup_s": round(setup_s, 2),
                    "operator_residual_ms": round(op_ms, 4), **extra},
