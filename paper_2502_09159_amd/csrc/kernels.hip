@@ -2305,15 +2305,14 @@ __global__ void k_ppass(const T* __restrict__ in, T* __restrict__ out, int nslic
                         int64_t slab_in, int64_t off_in, int64_t Mp_in, int64_t slab_out, int64_t off_out,
                         int64_t Mp_out, int d, int n_out, int n_in, int C_out, int C_in, const T* __restrict__ E,
                         int npos, int dir, int Cf, int Cc) {
-  int64_t ncell = 1;
-  for (int j = 0; j < d; ++j) ncell *= n_out;
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)nslices * ncell * C_out) return;
-  int l = (int)(idx % C_out);
-  int64_t c = (idx / C_out) % ncell;
-  int s = (int)(idx / (C_out * ncell));
-  int n = s / nt_out, a = s % nt_out;
-  int cc[3] = {(int)(c % n_out), (int)((c / n_out) % n_out), (int)(c / ((int64_t)n_out * n_out))};
+  // 32-bit index arithmetic: the launchers keep nslices * ncell * C_out below 2^31
+  const unsigned no = (unsigned)n_out, ncell = d == 3 ? no * no * no : no * no;
+  const unsigned idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (unsigned)nslices * ncell * (unsigned)C_out) return;
+  const unsigned l = idx % (unsigned)C_out, q = idx / (unsigned)C_out, c = q % ncell, s = q / ncell;
+  const int n = (int)(s / (unsigned)nt_out), a = (int)(s % (unsigned)nt_out);
+  const unsigned rr = c / no;
+  const int cc[3] = {(int)(c - rr * no), (int)(d == 3 ? rr % no : rr), (int)(d == 3 ? rr / no : 0u)};
   const T* src = in + (int64_t)n * slab_in + off_in + (int64_t)a * Mp_in;
   T* dst = out + (int64_t)n * slab_out + off_out + (int64_t)a * Mp_out;
   T v = 0;
@@ -2521,6 +2520,7 @@ hipError_t launch_prolongate_add(const LevelArgs& F, const LevelArgs& Cs, const 
   space_velocity<T>(Cs, F, F.nt, F.N, P1, rlo, rhi, t.max_row_p1, t.vt_p1, t.cap_p1, t.brk_p1, src, li, xf, lo,
                     tmp1, tmp2, false, s);
   int64_t tot = (int64_t)F.N * F.nt * (int64_t)(F.Mp);
+  if (tot >= (int64_t)1 << 31) return hipErrorInvalidValue;
   k_ppass<T><<<nblk(tot), 256, 0, s>>>(src, xf, F.N * F.nt, nt_src, F.nt, slab_src, (int64_t)nt_src * Cs.Mv, Cs.Mp,
                                        F.slab, (int64_t)F.nt * F.Mv, F.Mp, F.d, F.n, Cs.n, F.C, Cs.C, E, t.npos, 0,
                                        F.C, Cs.C);
@@ -2540,6 +2540,7 @@ hipError_t launch_restrict(const LevelArgs& F, const LevelArgs& Cs, const Transf
   int64_t ncc = 1;
   for (int j = 0; j < F.d; ++j) ncc *= Cs.n;
   int64_t tot = (int64_t)F.N * F.nt * ncc * Cs.C;
+  if (tot >= (int64_t)1 << 31) return hipErrorInvalidValue;
   k_ppass<T><<<nblk(tot), 256, 0, s>>>(rf, dst, F.N * F.nt, F.nt, F.nt, F.slab, (int64_t)F.nt * F.Mv, F.Mp, slab_dst,
                                        (int64_t)F.nt * Cs.Mv, Cs.Mp, F.d, Cs.n, F.n, Cs.C, F.C, E, t.npos, 1, F.C,
                                        Cs.C);
